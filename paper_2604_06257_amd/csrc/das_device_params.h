@@ -1,0 +1,17 @@
+// Kernel parameter block (plain data shared by host and device code).
+#pragma once
+
+#include <stdint.h>
+
+struct das_kparams {
+    int32_t T, E, S, F;
+    int64_t n_slots;     // tiles * slots per tile
+    int32_t n_tiles;
+    int32_t use_apod;    // f# > 0
+    double inv_c;        // 1 / c
+    double fs;
+    double fd;
+    double t0;
+    float two_fnum;      // 2 f#
+    float alpha;         // Tukey taper fraction
+};

@@ -1,0 +1,52 @@
+// Internal interfaces between the C ABI (das_api.cpp) and the kernels
+// (das_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "das_device_params.h"
+
+namespace das {
+
+constexpr int kWaves = 4;               // waves per workgroup tile
+constexpr int kLanes = 64;              // gfx950 wavefront
+constexpr int kSlots = kWaves * kLanes; // voxel slots per tile
+
+// Host-side voxel tiling: slot -> voxel index (-1 = empty slot).
+struct Tiling {
+    int32_t tile_dims[3] = {0, 0, 0};   // lattice points per tile (0: not a lattice)
+    int32_t wave_dims[3] = {0, 0, 0};   // lattice points per wave
+    int64_t n_tiles = 0;
+    std::vector<int32_t> slot_to_vox;   // n_tiles * kSlots
+};
+
+// Returns 0 or a negative das_status; err receives a message.
+int tile_points(const float* xyz, int64_t n, const char* override_spec, Tiling& out, std::string& err);
+
+struct PlanDev {
+    das_kparams kp;
+    float* vx = nullptr;       // [n_slots]
+    float* vy = nullptr;
+    float* vz = nullptr;
+    float* tx = nullptr;       // [T][n_slots]
+    int32_t* slot_vox = nullptr;  // [n_slots]
+    float* elem = nullptr;     // [E][3]
+    int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows)
+};
+
+// Computes per (tile, transmit, element) sample windows and counts.
+// counts[0] = active (slot, e, t) triples (w > 0, inside the record);
+// counts[1] = processed triples (valid slots of tiles whose window is not
+// empty); counts[2] = largest window.
+hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipStream_t s);
+
+hipError_t launch_das(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s);
+
+hipError_t launch_tx_plane_wave(float* tx_out, const float* vox_xyz, int64_t n_vox, const double* normals_host,
+                                int32_t n_tx, double inv_c, hipStream_t s);
+
+}  // namespace das

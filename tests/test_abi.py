@@ -1,0 +1,156 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+rejects bad arguments before touching the GPU, and tiles voxel sets correctly.
+No compute call is made here (there may be no GPU)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2604_06257_amd as das
+from paper_2604_06257_amd import _lib
+from synth import make_config, grid_3d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "das.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(das_\w+)\s*\(", text)))
+
+
+def test_header_declares_what_the_binding_expects():
+    assert declared_functions() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.das_version() >> 16 == 1
+
+
+def test_status_strings():
+    lib = _lib.load()
+    assert lib.das_status_string(0) == b"ok"
+    for code in range(-6, 0):
+        assert lib.das_status_string(code) not in (b"ok", b"unknown status")
+    assert lib.das_status_string(-99) == b"unknown status"
+
+
+def _params(**kw):
+    base = dict(n_tx=1, n_elem=4, n_samples=16, n_frames=2, n_vox=8, sound_speed=1540.0, fs=20e6, f_demod=5e6,
+                t0=0.0, f_number=1.0, tukey_alpha=0.5)
+    base.update(kw)
+    return das.Params(**base).to_c()
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: the argument checks fail first
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_tx=0), _lib.DAS_ESHAPE), (dict(n_elem=0), _lib.DAS_ESHAPE), (dict(n_samples=0), _lib.DAS_ESHAPE),
+    (dict(n_frames=0), _lib.DAS_ESHAPE), (dict(n_vox=-1), _lib.DAS_ESHAPE), (dict(sound_speed=0.0), _lib.DAS_EINVAL),
+    (dict(sound_speed=float("nan")), _lib.DAS_EINVAL), (dict(fs=-1.0), _lib.DAS_EINVAL),
+    (dict(f_demod=-1.0), _lib.DAS_EINVAL), (dict(t0=float("inf")), _lib.DAS_EINVAL),
+    (dict(f_number=-0.5), _lib.DAS_EINVAL), (dict(tukey_alpha=1.5), _lib.DAS_EINVAL),
+    (dict(n_vox=2**31), _lib.DAS_ESHAPE),
+])
+def test_plan_create_rejects_bad_params(kw, status):
+    lib = _lib.load()
+    h = ctypes.c_void_p(0)
+    p = _params(**kw)
+    assert lib.das_plan_create(ctypes.byref(h), ctypes.byref(p), FAKE, FAKE, FAKE, None) == status
+    assert h.value is None
+    assert len(lib.das_last_error()) > 0
+
+
+def test_plan_create_rejects_null_and_misaligned():
+    lib = _lib.load()
+    h = ctypes.c_void_p(0)
+    p = _params()
+    assert lib.das_plan_create(None, ctypes.byref(p), FAKE, FAKE, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_plan_create(ctypes.byref(h), None, FAKE, FAKE, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_plan_create(ctypes.byref(h), ctypes.byref(p), None, FAKE, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_plan_create(ctypes.byref(h), ctypes.byref(p), FAKE, None, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_plan_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(0x1002), FAKE, FAKE,
+                               None) == _lib.DAS_EALIGN
+
+
+def test_execute_and_query_reject_dead_plans():
+    lib = _lib.load()
+    assert lib.das_execute(None, FAKE, 0, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_execute(ctypes.c_void_p(0x4000), FAKE, 0, FAKE, None) == _lib.DAS_EINVAL  # never created
+    info = _lib.DasPlanInfo()
+    assert lib.das_plan_query(None, ctypes.byref(info)) == _lib.DAS_EINVAL
+    assert lib.das_plan_destroy(None) == _lib.DAS_OK
+    assert lib.das_plan_destroy(ctypes.c_void_p(0x4000)) == _lib.DAS_EINVAL
+
+
+def test_tx_plane_wave_rejects_bad_args():
+    lib = _lib.load()
+    ang = (ctypes.c_double * 2)(0.0, 0.0)
+    assert lib.das_tx_plane_wave(FAKE, FAKE, 10, ang, 0, 1540.0, None) == _lib.DAS_ESHAPE
+    assert lib.das_tx_plane_wave(FAKE, FAKE, 10, None, 1, 1540.0, None) == _lib.DAS_EINVAL
+    assert lib.das_tx_plane_wave(FAKE, FAKE, 10, ang, 1, 0.0, None) == _lib.DAS_EINVAL
+    assert lib.das_tx_plane_wave(None, FAKE, 10, ang, 1, 1540.0, None) == _lib.DAS_EINVAL
+    bad = (ctypes.c_double * 2)(float("nan"), 0.0)
+    assert lib.das_tx_plane_wave(FAKE, FAKE, 10, bad, 1, 1540.0, None) == _lib.DAS_EINVAL
+
+
+# ----------------------------------------------------------------- tiling
+def _check_bijection(s2v, n):
+    assert s2v.size % 256 == 0
+    got = np.sort(s2v[s2v >= 0])
+    np.testing.assert_array_equal(got, np.arange(n))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c2_251", "c3"])
+def test_tiling_of_config_grids(name):
+    cfg = make_config(name, with_iq=False)
+    vox = cfg["vox"]
+    s2v, dims = das.tile_order(vox)
+    _check_bijection(s2v, vox.shape[0])
+    assert dims == ((8, 8, 4) if name == "c3" else (32, 1, 8))
+    # every tile is a compact lattice patch: its extent matches the tile shape
+    step = 0.1e-3 if name != "c1" else None
+    tiles = s2v.reshape(-1, 256)
+    for t in tiles[:: max(1, len(tiles) // 17)]:
+        pts = vox[t[t >= 0]]
+        ext = pts.max(0) - pts.min(0)
+        if step is not None:
+            assert ext[0] <= (dims[0] - 1) * step * 1.0001 + 1e-9
+            assert ext[2] <= (dims[2] - 1) * step * 1.0001 + 1e-9
+    # 16-lane rows of each wave share one depth (bank-conflict-free LDS reads along a lateral row)
+    w = tiles[0].reshape(4, 4, 16)
+    for wave in w:
+        for row in wave:
+            ok = row[row >= 0]
+            assert np.unique(vox[ok][:, 2]).size <= 1
+
+
+def test_tiling_partial_lattice_and_point_cloud():
+    xs = (np.arange(40) - 20) * 1e-4
+    zs = 1e-3 + np.arange(30) * 1e-4
+    full = grid_3d(xs, [0.0], zs)
+    keep = np.random.default_rng(0).uniform(size=full.shape[0]) < 0.7
+    part = full[keep]
+    s2v, dims = das.tile_order(part)
+    _check_bijection(s2v, part.shape[0])
+    assert dims == (32, 1, 8)
+    cloud = np.random.default_rng(1).uniform(-1, 1, (1000, 3)).astype(np.float32)
+    s2v, dims = das.tile_order(cloud)
+    _check_bijection(s2v, 1000)
+    assert dims == (0, 0, 0)
+    # repeated points are not a lattice but are all kept
+    rep = np.concatenate([part[:10], part[:10]])
+    s2v, dims = das.tile_order(rep)
+    _check_bijection(s2v, 20)
+    s2v, dims = das.tile_order(np.zeros((0, 3), np.float32))
+    assert s2v.size == 0
+    with pytest.raises(ValueError):
+        das.tile_order(np.array([[0.0, 0.0, np.nan]], np.float32))
