@@ -1,0 +1,213 @@
+"""Throughput benchmark of the gfx950 delay-and-sum path.
+
+One step = one das_execute of the whole workload: every voxel, element,
+transmit and frame (paper Eq. 1 points), inputs resident in HBM.  Default
+workload: the rotating-disk stand-in (128-element linear array, 1 plane
+wave, 32 frames of 2048 complex64 samples, 256 x 256 grid at 0.1 mm,
+f-number 1), i.e. 268,435,456 points per step.
+
+Prints one JSON line with points/s, the roofline of the dominant kernel and
+the FP64 oracle timed on the host cores (run before the GPU is touched).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from synth import make_config  # noqa: E402
+
+WORKLOADS = {
+    "c2": "rotating-disk stand-in: 128-el linear array (0.3 mm), 1 plane wave at 0 deg, 32 frames x 2048 samples "
+          "complex64 IQ (fc = fd = 5 MHz, fs = 20 MHz), 256 x 256 grid at 0.1 mm, f# 1.0 Tukey(0.5)",
+    "c2_251": "paper-exact grid of the rotating-disk benchmark: as c2 with 251 x 251 voxels",
+    "c1": "2D plane wave, 128-el linear array, 1 transmit, 1 frame x 1024 samples, 128 x 128 grid, f# 1.5",
+    "c3": "3D: 32 x 32 matrix array, 5 elevation plane waves, 8 frames x 2048 samples, 96^3 grid, f# 1.0",
+}
+FLOP_PER_POINT = 16          # two complex multiply-accumulates per (voxel, element, transmit, frame)
+PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
+PAPER_PTS_PER_S = 258052096 / 0.23e-3   # RTX 5090, 251 x 251 rotating disk (context only)
+
+
+def _cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+_SHARED = {}
+
+
+def _oracle_chunk(bounds):
+    import oracle
+    a, b = bounds
+    s = _SHARED
+    return a, oracle.das(s["iq"], s["elem"], s["vox"][a:b], s["tx"][:, a:b], **s["p"])
+
+
+def cpu_baseline(cfg, max_voxels):
+    """FP64 oracle on the host cores (fork pool over voxel chunks)."""
+    import multiprocessing as mp
+
+    import oracle
+    p = cfg["params"]
+    vox = cfg["vox"][:max_voxels]
+    tx = oracle.tx_plane_wave(vox, cfg["angles"], p["c"]).astype(np.float32)
+    _SHARED.update(iq=cfg["iq"], elem=cfg["elem"], vox=vox, tx=tx,
+                   p=dict(c=p["c"], fs=p["fs"], fd=p["fd"], t0=p["t0"], f_number=p["f_number"],
+                          tukey_alpha=p["tukey_alpha"]))
+    cores = _cores()
+    V = vox.shape[0]
+    chunk = max(1, -(-V // (4 * cores)))
+    bounds = [(a, min(V, a + chunk)) for a in range(0, V, chunk)]
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        parts = pool.map(_oracle_chunk, bounds)
+    dt = time.perf_counter() - t0
+    y = np.zeros((V, p["n_frames"]), np.complex128)
+    for a, part in parts:
+        y[a:a + part.shape[0]] = part
+    T, E = cfg["iq"].shape[:2]
+    pts = V * E * T * p["n_frames"]
+    return y, {"value": pts / dt, "unit": "points/s", "cores": cores, "kind": "oracle", "seconds": round(dt, 3),
+               "sample": "%d voxels (all %d elements, %d transmit(s), %d frames) = %d points of one step, "
+                         "voxel chunks over %d processes" % (V, E, T, p["n_frames"], pts, cores)}
+
+
+def time_steps(plan, iq, out, steps, warmup, torch):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.execute(iq, out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.execute(iq, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP16 / BF16 IQ timings")
+    ap.add_argument("--cpu-voxels", type=int, default=None, help="voxels in the oracle sample (default: all)")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="also run a torch copy of this many GiB (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build's path runs on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    cfg = make_config(args.workload)
+    p = cfg["params"]
+    iq_np = cfg["iq"]
+    T, E, S, F = iq_np.shape
+    V = cfg["vox"].shape[0]
+    points = V * E * T * F
+
+    ref = base = None
+    if not args.no_cpu_baseline:
+        nv = V if args.cpu_voxels is None else min(V, args.cpu_voxels)
+        ref, base = cpu_baseline(cfg, nv)
+
+    import torch
+
+    import oracle
+    import paper_2604_06257_amd as das
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    vox = dev(cfg["vox"])
+    tx = das.tx_plane_wave(vox, cfg["angles"], p["c"])
+    params = das.Params(T, E, S, F, V, p["c"], p["fs"], p["fd"], p["t0"], p["f_number"], p["tukey_alpha"])
+    plan = das.Plan(params, dev(cfg["elem"]), vox, tx)
+    info = plan.info()
+    iq = dev(iq_np)
+    out = torch.empty((V, F), dtype=torch.complex64, device="cuda")
+    ms, wall = time_steps(plan, iq, out, args.steps, args.warmup, torch)
+    value = points / (ms * 1e-3)
+
+    active_pts = info["active_triples"] * F
+    achieved_tflops = active_pts * FLOP_PER_POINT / (ms * 1e-3) / 1e12
+    result = {
+        "metric": "points/s (voxel x element x tx x frame) FP32 vs FP16-IQ, error in dB vs FP64",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload + ": " + WORKLOADS[args.workload], "voxels": V, "elements": E,
+                   "transmits": T, "frames": F, "samples": S, "points_per_step": points, "iq": "complex64",
+                   "parallelism": "single GPU"},
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "active_points_per_s": active_pts / (ms * 1e-3),
+        "active_fraction": info["active_triples"] / max(1, info["total_triples"]),
+        "processed_fraction": info["processed_triples"] / max(1, info["total_triples"]),
+        "plan": {"tiles": info["n_tiles"], "tile_dims": info["tile_dims"], "max_window": info["max_window"]},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "das_kernel<32,65,c64>",
+                     "work": "%d FLOP x active points (w > 0, inside the record) per launch" % FLOP_PER_POINT},
+        "paper_context": {"points_per_s": PAPER_PTS_PER_S, "hardware": "NVIDIA GeForce RTX 5090",
+                          "workload": "PyMUST rotating disk 251 x 251, 32 frames"},
+    }
+    y = out.cpu().numpy()
+    if ref is not None:
+        nv = ref.shape[0]
+        result["nrmse_db_vs_fp64"] = oracle.nrmse_db(y[:nv], ref)
+        result["peak_err_db_vs_fp64"] = oracle.peak_err_db(y[:nv], ref)
+        result["cpu_baseline"] = base
+    if not args.no_variants:
+        var = {}
+        ri = torch.view_as_real(iq)
+        for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            iq16 = ri.to(dt).contiguous()
+            out16 = torch.empty_like(out)
+            ms16, _ = time_steps(plan, iq16, out16, args.steps, args.warmup, torch)
+            v = {"value": points / (ms16 * 1e-3), "ms_per_step": ms16, "dtype": "f32 (IQ stored %s)" % name}
+            if ref is not None:
+                y16 = out16.cpu().numpy()
+                v["nrmse_db_vs_fp64"] = oracle.nrmse_db(y16[:ref.shape[0]], ref)
+            var[name] = v
+            del iq16
+        result["iq16_variants"] = var
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = 4 * n
+    plan.close()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()
