@@ -68,7 +68,8 @@ enum das_iq_dtype {
 typedef struct das_params {
     int32_t n_tx;        /* T >= 1: transmits (compounded plane waves)       */
     int32_t n_elem;      /* E >= 1: receive elements (channels)              */
-    int32_t n_samples;   /* S >= 1: samples per record                       */
+    int32_t n_samples;   /* S >= 1: samples per record; (S + 4200) * F * 8
+                            bytes must stay below 2 GiB                      */
     int32_t n_frames;    /* F >= 1: frames (ensemble)                        */
     int64_t n_vox;       /* V >= 0: output points                            */
     double sound_speed;  /* c > 0 [m/s]                                      */

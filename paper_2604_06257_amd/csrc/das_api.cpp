@@ -217,6 +217,9 @@ static int check_params(const das_params* p) {
     if (p->n_vox > (int64_t)INT32_MAX) return fail(DAS_ESHAPE, "more than 2^31 - 1 voxels");
     if ((double)p->n_tx * (double)p->n_elem > (double)INT32_MAX)
         return fail(DAS_ESHAPE, "T * E must fit in 31 bits");
+    // one (t, e) record is addressed with 32-bit byte offsets (plus a window margin)
+    if (((double)p->n_samples + 4200.0) * (double)p->n_frames * 8.0 > (double)INT32_MAX)
+        return fail(DAS_ESHAPE, "a (transmit, element) record of S * F samples must stay below 2 GiB");
     if (!(std::isfinite(p->sound_speed) && p->sound_speed > 0)) return fail(DAS_EINVAL, "sound_speed must be finite and > 0");
     if (!(std::isfinite(p->fs) && p->fs > 0)) return fail(DAS_EINVAL, "fs must be finite and > 0");
     if (!(std::isfinite(p->f_demod) && p->f_demod >= 0)) return fail(DAS_EINVAL, "f_demod must be finite and >= 0");
@@ -232,7 +235,7 @@ static bool plan_live(const das_plan* plan) {
 }
 
 static void free_dev(das::PlanDev& d) {
-    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows};
+    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows, d.items, d.item_off};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = das::PlanDev();
@@ -341,6 +344,7 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
     kp.t0 = p->t0;
     kp.two_fnum = (float)(2.0 * p->f_number);
     kp.alpha = (float)p->tukey_alpha;
+    kp.inv_2alpha = p->tukey_alpha > 0 ? (float)(0.5 / p->tukey_alpha) : 0.0f;
 
     unsigned long long* counts = nullptr;
     unsigned long long hc[3] = {0, 0, 0};
@@ -361,6 +365,42 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
     plan->active_triples = (int64_t)hc[0];
     plan->processed_triples = (int64_t)hc[1];
     plan->max_window = (int32_t)hc[2];
+    {
+        // Work items per tile: the non-empty (t, e) windows, cut into pieces of at
+        // most pitch - 1 rows, element-major so consecutive items share the
+        // receive geometry.
+        const das::Variant var = das::choose_variant(p->n_frames, plan->max_window);
+        d.fc = var.fc;
+        d.pitch = var.pitch;
+        d.groups = var.groups;
+        const int rows = var.pitch - 1;
+        std::vector<int32_t> win((size_t)2 * tl.n_tiles * T * E);
+        if (!win.empty() &&
+            (e = hipMemcpy(win.data(), d.windows, win.size() * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+            goto hip_fail;
+        std::vector<int4> items;
+        std::vector<int32_t> off((size_t)tl.n_tiles + 1, 0);
+        for (int64_t t = 0; t < tl.n_tiles; ++t) {
+            off[t] = (int32_t)items.size();
+            for (int64_t el = 0; el < E; ++el)
+                for (int64_t k = 0; k < T; ++k) {
+                    const int32_t* w = &win[2 * ((t * T + k) * E + el)];
+                    for (int32_t r = 0; r < w[1]; r += rows)
+                        items.push_back(make_int4((int)k, (int)el, w[0] + r, std::min(rows, w[1] - r)));
+                }
+            if (items.size() > (size_t)INT32_MAX) {
+                e = hipErrorInvalidValue;
+                goto hip_fail;
+            }
+        }
+        off[tl.n_tiles] = (int32_t)items.size();
+        (void)hipFree(d.windows);
+        d.windows = nullptr;
+        if ((e = upload(&d.items, items, s)) != hipSuccess || (e = upload(&d.item_off, off, s)) != hipSuccess)
+            goto hip_fail;
+        if ((e = das::prepare_variant(d)) != hipSuccess) goto hip_fail;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) goto hip_fail;
+    }
     {
         std::lock_guard<std::mutex> g(g_mu);
         g_live.insert(plan);

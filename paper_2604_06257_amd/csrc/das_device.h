@@ -30,11 +30,12 @@ struct das_coef {
 };
 
 // Tukey window on the normalised lateral distance rho (0 outside rho < 1).
-__device__ __forceinline__ float das_tukey(float rho, float alpha) {
+// The taper cos(pi x) uses the hardware cosine, whose argument is in turns.
+__device__ __forceinline__ float das_tukey(float rho, float alpha, float inv_2alpha) {
     if (!(rho < 1.0f)) return 0.0f;
     const float edge = 1.0f - alpha;
     if (rho <= edge) return 1.0f;
-    return 0.5f + 0.5f * cospif((rho - edge) / alpha);
+    return 0.5f + 0.5f * __builtin_amdgcn_cosf((rho - edge) * inv_2alpha);
 }
 
 __device__ __forceinline__ das_rx das_rx_setup(float vx, float vy, float vz, float ex, float ey, float ez,
@@ -50,8 +51,8 @@ __device__ __forceinline__ das_rx das_rx_setup(float vx, float vy, float vz, flo
         o.w = 0.0f;
     } else {
         const float lat = sqrtf((float)(dx * dx + dy * dy));
-        const float rho = kp.two_fnum * lat / (float)dz;
-        o.w = das_tukey(rho, kp.alpha);
+        const float rho = kp.two_fnum * lat * __builtin_amdgcn_rcpf((float)dz);
+        o.w = das_tukey(rho, kp.alpha, kp.inv_2alpha);
     }
     return o;
 }
@@ -65,10 +66,10 @@ __device__ __forceinline__ das_coef das_tx_setup(const das_rx& rx, float tx_arri
     o.i0 = o.active ? (int)fl : 0;
     o.beta = (float)(u - fl);
     double ph = kp.fd * tau;
-    ph -= rint(ph);  // carrier phase in cycles, in [-0.5, 0.5]
-    float s, c;
-    sincospif(2.0f * (float)ph, &s, &c);
-    o.cr = rx.w * c;
-    o.ci = rx.w * s;
+    ph -= rint(ph);  // carrier phase in turns, in [-0.5, 0.5]
+    // v_sin_f32 / v_cos_f32 take turns; max error 1.3e-7 on [-0.5, 0.5]
+    const float pf = (float)ph;
+    o.cr = rx.w * __builtin_amdgcn_cosf(pf);
+    o.ci = rx.w * __builtin_amdgcn_sinf(pf);
     return o;
 }

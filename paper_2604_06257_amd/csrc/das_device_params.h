@@ -14,4 +14,6 @@ struct das_kparams {
     double t0;
     float two_fnum;      // 2 f#
     float alpha;         // Tukey taper fraction
+    float inv_2alpha;    // 1 / (2 alpha), 0 when alpha = 0
+    int32_t vec_ok;      // frame rows are 16-byte aligned (F multiple of the vector width)
 };

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
 #include <stdint.h>
 
 #include <string>
@@ -35,14 +36,26 @@ struct PlanDev {
     float* tx = nullptr;       // [T][n_slots]
     int32_t* slot_vox = nullptr;  // [n_slots]
     float* elem = nullptr;     // [E][3]
-    int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows)
+    int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows); plan-time only
+    int4* items = nullptr;      // per tile, the (t, e, first row, rows) work items, e-major
+    int32_t* item_off = nullptr;  // [n_tiles + 1] offsets into items
+    int32_t fc = 0, pitch = 0, groups = 1;  // kernel variant: frames per workgroup, LDS row pitch, element groups
 };
+
+// Kernel variant for F frames and the largest tile window (rows).
+struct Variant {
+    int fc, pitch, groups;
+};
+Variant choose_variant(int frames, int max_window);
 
 // Computes per (tile, transmit, element) sample windows and counts.
 // counts[0] = active (slot, e, t) triples (w > 0, inside the record);
 // counts[1] = processed triples (valid slots of tiles whose window is not
 // empty); counts[2] = largest window.
 hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipStream_t s);
+
+// Raises the dynamic LDS limit of the plan's kernel variant (all IQ types).
+hipError_t prepare_variant(const PlanDev& p);
 
 hipError_t launch_das(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s);
 

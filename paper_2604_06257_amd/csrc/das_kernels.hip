@@ -33,31 +33,44 @@
 namespace das {
 
 // ---------------------------------------------------------------- IQ loads
+// Complex samples are read in groups of FPT consecutive frames of one sample
+// row: one 16-, 8- or 4-byte load, kept raw in registers until the LDS write.
+template <int BYTES>
+struct RawT;
+template <>
+struct RawT<16> {
+    using type = uint4;
+};
+template <>
+struct RawT<8> {
+    using type = uint2;
+};
+template <>
+struct RawT<4> {
+    using type = uint32_t;
+};
+
 template <int DT>
-struct IQLoad;
-
-template <>
-struct IQLoad<DAS_IQ_C64> {
-    __device__ static float2 at(const void* base, size_t i) {
-        return reinterpret_cast<const float2*>(base)[i];
-    }
+struct IQType {
+    static constexpr int kBytes = (DT == DAS_IQ_C64) ? 8 : 4;  // bytes per complex sample
+    static constexpr int kVec = 16 / kBytes;                    // complex samples per 16 bytes
 };
 
-template <>
-struct IQLoad<DAS_IQ_C16F> {
-    __device__ static float2 at(const void* base, size_t i) {
-        const __half2 h = reinterpret_cast<const __half2*>(base)[i];
-        return __half22float2(h);
-    }
-};
-
-template <>
-struct IQLoad<DAS_IQ_C16BF> {
-    __device__ static float2 at(const void* base, size_t i) {
-        const uint32_t u = reinterpret_cast<const uint32_t*>(base)[i];
+// Frame j of a raw group, as FP32 (re, im).
+template <int DT, typename R>
+__device__ __forceinline__ float2 decode(const R& raw, int j) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(&raw);
+    if constexpr (DT == DAS_IQ_C64) {
+        return make_float2(__uint_as_float(w[2 * j]), __uint_as_float(w[2 * j + 1]));
+    } else if constexpr (DT == DAS_IQ_C16F) {
+        const uint32_t u = w[j];
+        return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(u >> 16))));
+    } else {
+        const uint32_t u = w[j];
         return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
     }
-};
+}
 
 // Workgroup id -> tile so that each XCD (workgroups are dispatched round-robin
 // over the 8 XCDs) works on one contiguous run of tiles: neighbouring tiles
@@ -139,18 +152,43 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 }
 
 // ------------------------------------------------------------- main kernel
-// FC frames per workgroup, P = LDS row pitch in 16-byte units (P - 1 rows of
-// window per pass; P odd so that frame rows start in different bank groups).
-template <int FC, int P, int DT>
-__global__ __launch_bounds__(kSlots) void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out) {
-    __shared__ float4 lds[FC * P];
+// FC frames per workgroup; P = LDS row pitch in 16-byte units (P - 1 window
+// rows per item, P odd so consecutive frame rows start in different banks);
+// G element groups of 4 waves share the tile: group g takes items g, g + G,
+// ... and the groups' partial sums are added in a fixed order at the end.
+//
+// Software pipeline (per group, item k, prefetch depth 2):
+//   write the window of item k (registers, loaded two items ago) to LDS
+//   buffer k & 1 as rows (q[s], q[s+1] - q[s]); barrier
+//   issue the global loads of item k + 2G into the freed registers
+//   coefficients of item k (FP64), then FC frames of one LDS read + six FMAs
+// Fill: thread -> (frame group of FPT frames, run of RPT rows); it loads RPT + 1
+// rows of its frames (each sample once) with 16-byte loads when aligned.
+template <int FC, int P, int DT, int G>
+__global__ __launch_bounds__(kSlots* G) void das_kernel(PlanDev p, const void* __restrict__ iq,
+                                                       float2* __restrict__ out, int vec) {
     constexpr int kRows = P - 1;
+    constexpr int kBuf = FC * P;  // float4 per buffer
+    constexpr int kEB = IQType<DT>::kBytes;
+    constexpr int FPT = FC < IQType<DT>::kVec ? FC : IQType<DT>::kVec;  // frames per fill thread
+    constexpr int NFG = FC / FPT;                                      // frame groups per row
+    constexpr int RPT = (kRows * NFG + kSlots - 1) / kSlots;           // rows per fill thread
+    using Raw = typename RawT<FPT * kEB>::type;
+    extern __shared__ float4 lds[];  // [G][2][FC][P]
     const das_kparams& kp = p.kp;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int f0 = blockIdx.y * FC;
-    const int64_t slot = (int64_t)tile * kSlots + threadIdx.x;
+    // group index is wave-uniform (a group is 4 whole waves); say so to the compiler
+    const int grp = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kSlots));
+    const int gt = threadIdx.x % kSlots;  // slot within the tile
+    const int64_t slot = (int64_t)tile * kSlots + gt;
     const int vox = p.slot_vox[slot];
     const float vx = p.vx[slot], vy = p.vy[slot], vz = p.vz[slot];
+    float4* buf0 = lds + grp * 2 * kBuf;
+    float4* buf1 = buf0 + kBuf;
+    const int fgrp = gt % NFG, row0 = (gt / NFG) * RPT;
+    const int fbase = f0 + fgrp * FPT;
+    const bool full_frames = vec && (fbase + FPT <= kp.F);
 
     float acc_r[FC], acc_i[FC];
 #pragma unroll
@@ -158,55 +196,139 @@ __global__ __launch_bounds__(kSlots) void das_kernel(PlanDev p, const void* __re
         acc_r[f] = 0.0f;
         acc_i[f] = 0.0f;
     }
-    const int32_t* wins = p.windows + 2 * (int64_t)tile * kp.T * kp.E;
+    const int first = p.item_off[tile];
+    const int nitems = p.item_off[tile + 1] - first;
+    const int4* items = p.items + first;
+    const int nsteps = (nitems + G - 1) / G;
 
-    for (int e = 0; e < kp.E; ++e) {
-        bool have_rx = false;
-        das_rx rx;
-        for (int t = 0; t < kp.T; ++t) {
-            const int lo0 = wins[2 * (t * kp.E + e)];
-            const int nrow = wins[2 * (t * kp.E + e) + 1];
-            if (nrow == 0) continue;  // no lane of the tile sees this (t, e)
-            if (!have_rx) {
-                rx = das_rx_setup(vx, vy, vz, p.elem[3 * e], p.elem[3 * e + 1], p.elem[3 * e + 2], kp);
-                have_rx = true;
-            }
-            const das_coef c = das_tx_setup(rx, p.tx[(int64_t)t * kp.n_slots + slot], kp);
-            const bool act = (vox >= 0) && c.active;
-            const size_t rec = ((size_t)t * kp.E + e) * (size_t)kp.S;  // record start, in samples
-            for (int pass = 0; pass < nrow; pass += kRows) {
-                const int lo = lo0 + pass;
-                const int n = min(kRows, nrow - pass);
-                __syncthreads();  // previous readers of lds are done
-                for (int idx = threadIdx.x; idx < n * FC; idx += kSlots) {
-                    const int row = idx / FC, f = idx % FC;
-                    const int s = lo + row;
-                    const int fg = f0 + f;
-                    float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
-                    if (fg < kp.F) {
-                        if (s >= 0 && s < kp.S) a = IQLoad<DT>::at(iq, (rec + s) * kp.F + fg);
-                        if (s + 1 >= 0 && s + 1 < kp.S) b = IQLoad<DT>::at(iq, (rec + s + 1) * kp.F + fg);
-                    }
-                    lds[f * P + row] = make_float4(a.x, a.y, b.x - a.x, b.y - a.y);
-                }
-                __syncthreads();
-                if (act && c.i0 >= lo && c.i0 < lo + n) {
-                    const float4* src = lds + (c.i0 - lo);
+    // Channel data of one (t, e) record through a buffer resource: offsets
+    // outside [0, S * F) samples (rows before 0 or past S - 1) read as zero,
+    // which is the zero padding of the record.
+    const int64_t rec_bytes = (int64_t)kp.S * kp.F * kEB;
+    const int lane_off = (row0 * kp.F + fbase) * kEB;  // this thread's first row and frames
+    const int row_bytes = kp.F * kEB;
+    const bool fill_frames = fbase < kp.F;
+    auto load_item = [&](int k, Raw (&raw)[RPT + 1], float& txv, int4& it) {
+        it = items[k];
+        txv = p.tx[(int64_t)it.x * kp.n_slots + slot];
+        const char* rec = reinterpret_cast<const char*>(iq) + ((int64_t)it.x * kp.E + it.y) * rec_bytes;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
+        const int off0 = it.z * row_bytes + lane_off;
+        if (row0 < it.w && fill_frames) {
 #pragma unroll
-                    for (int f = 0; f < FC; ++f) {
-                        const float4 d = src[f * P];
-                        const float tr = fmaf(c.beta, d.z, d.x);
-                        const float ti = fmaf(c.beta, d.w, d.y);
-                        acc_r[f] = fmaf(c.cr, tr, acc_r[f]);
-                        acc_r[f] = fmaf(-c.ci, ti, acc_r[f]);
-                        acc_i[f] = fmaf(c.cr, ti, acc_i[f]);
-                        acc_i[f] = fmaf(c.ci, tr, acc_i[f]);
+            for (int j = 0; j <= RPT; ++j) {
+                const int off = off0 + j * row_bytes;
+                if (full_frames) {
+                    if constexpr (sizeof(Raw) == 16) {
+                        raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+                    } else if constexpr (sizeof(Raw) == 8) {
+                        raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                    } else {
+                        raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                    }
+                } else {
+                    // unaligned rows or the last partial frame group: one sample at a time
+                    uint32_t* w = reinterpret_cast<uint32_t*>(&raw[j]);
+#pragma unroll
+                    for (int q = 0; q < FPT; ++q) {
+                        if (kEB == 8) {
+                            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + q * 8, 0, 0);
+                            w[2 * q] = (uint32_t)v[0];
+                            w[2 * q + 1] = (uint32_t)v[1];
+                        } else {
+                            w[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + q * 4, 0, 0);
+                        }
                     }
                 }
             }
         }
+    };
+    // LDS frame slot of frame f: frames of one fill thread go to slots NFG
+    // apart, so the 16 lanes of a write hit 16 different bank groups.
+    auto store_item = [&](const int4& it, const Raw (&raw)[RPT + 1], float4* buf) {
+        if (row0 < it.w && fill_frames) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+#pragma unroll
+                for (int q = 0; q < FPT; ++q) {
+                    const float2 a = decode<DT>(raw[j], q), b = decode<DT>(raw[j + 1], q);
+                    buf[(fgrp + q * NFG) * P + row0 + j] = make_float4(a.x, a.y, b.x - a.x, b.y - a.y);
+                }
+            }
+        }
+    };
+    int last_e = -1;
+    das_rx rx;
+    auto compute_item = [&](const int4& it, float txv, const float4* buf) {
+        if (it.y != last_e) {
+            rx = das_rx_setup(vx, vy, vz, p.elem[3 * it.y], p.elem[3 * it.y + 1], p.elem[3 * it.y + 2], kp);
+            last_e = it.y;
+        }
+        const das_coef c = das_tx_setup(rx, txv, kp);
+        if (vox >= 0 && c.active && c.i0 >= it.z && c.i0 < it.z + it.w) {
+            const float4* src = buf + (c.i0 - it.z);
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                const float4 d = src[((f % FPT) * NFG + f / FPT) * P];
+                const float tr = fmaf(c.beta, d.z, d.x);
+                const float ti = fmaf(c.beta, d.w, d.y);
+                acc_r[f] = fmaf(c.cr, tr, acc_r[f]);
+                acc_r[f] = fmaf(-c.ci, ti, acc_r[f]);
+                acc_i[f] = fmaf(c.cr, ti, acc_i[f]);
+                acc_i[f] = fmaf(c.ci, tr, acc_i[f]);
+            }
+        }
+    };
+
+    Raw ra[RPT + 1], rb[RPT + 1];
+    float txa = 0.0f, txb = 0.0f;
+    int4 ita = make_int4(0, 0, 0, 0), itb = make_int4(0, 0, 0, 0);
+    if (grp < nitems) load_item(grp, ra, txa, ita);
+    if (grp + G < nitems) load_item(grp + G, rb, txb, itb);
+    for (int step = 0; step < nsteps; step += 2) {
+        {
+            const int k = step * G + grp;
+            const bool have = k < nitems;
+            const int4 it = ita;
+            if (have) store_item(it, ra, buf0);
+            __syncthreads();
+            const float txc = txa;
+            if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa, ita);
+            if (have) compute_item(it, txc, buf0);
+        }
+        if (step + 1 < nsteps) {
+            const int k = (step + 1) * G + grp;
+            const bool have = k < nitems;
+            const int4 it = itb;
+            if (have) store_item(it, rb, buf1);
+            __syncthreads();
+            const float txc = txb;
+            if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb, itb);
+            if (have) compute_item(it, txc, buf1);
+        }
     }
-    if (vox >= 0) {
+    if (G > 1) {
+        // fixed-order reduction of the groups' partial sums through LDS
+        float2* red = reinterpret_cast<float2*>(lds);  // [G-1][FC][kSlots]
+        __syncthreads();
+        if (grp > 0) {
+#pragma unroll
+            for (int f = 0; f < FC; ++f) red[((grp - 1) * FC + f) * kSlots + gt] = make_float2(acc_r[f], acc_i[f]);
+        }
+        __syncthreads();
+        if (grp == 0) {
+            for (int g = 1; g < G; ++g) {
+#pragma unroll
+                for (int f = 0; f < FC; ++f) {
+                    const float2 v = red[((g - 1) * FC + f) * kSlots + gt];
+                    acc_r[f] += v.x;
+                    acc_i[f] += v.y;
+                }
+            }
+        }
+    }
+    if (grp == 0 && vox >= 0) {
         float2* o = out + (size_t)vox * kp.F;
 #pragma unroll
         for (int f = 0; f < FC; ++f)
@@ -214,34 +336,93 @@ __global__ __launch_bounds__(kSlots) void das_kernel(PlanDev p, const void* __re
     }
 }
 
-template <int FC, int P>
-static hipError_t launch_fc(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
+template <int FC, int P, int G>
+static size_t lds_bytes() {
+    const size_t win = (size_t)G * 2 * FC * P * sizeof(float4);
+    const size_t red = (size_t)(G - 1) * FC * kSlots * sizeof(float2);
+    return win > red ? win : red;
+}
+
+// Vector (16/8/4-byte) loads need every frame group of every row aligned.
+template <int FC, int DT>
+static int vec_loads_ok(const PlanDev& p, const void* iq) {
+    constexpr int kEB = IQType<DT>::kBytes;
+    constexpr int FPT = FC < IQType<DT>::kVec ? FC : IQType<DT>::kVec;
+    return (p.kp.F % FPT == 0) && (reinterpret_cast<uintptr_t>(iq) % (FPT * kEB) == 0);
+}
+
+template <int FC, int P, int G>
+static hipError_t launch_v(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
     const dim3 grid(p.kp.n_tiles, (p.kp.F + FC - 1) / FC);
+    const dim3 block(kSlots * G);
+    const size_t sh = lds_bytes<FC, P, G>();
     float2* o = reinterpret_cast<float2*>(out);
     switch (dtype) {
         case DAS_IQ_C64:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C64>), grid, dim3(kSlots), 0, s, p, iq, o);
+            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C64, G>), grid, block, sh, s, p, iq, o,
+                               vec_loads_ok<FC, DAS_IQ_C64>(p, iq));
             break;
         case DAS_IQ_C16F:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16F>), grid, dim3(kSlots), 0, s, p, iq, o);
+            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16F, G>), grid, block, sh, s, p, iq, o,
+                               vec_loads_ok<FC, DAS_IQ_C16F>(p, iq));
             break;
         default:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16BF>), grid, dim3(kSlots), 0, s, p, iq, o);
+            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16BF, G>), grid, block, sh, s, p, iq, o,
+                               vec_loads_ok<FC, DAS_IQ_C16BF>(p, iq));
             break;
     }
     return hipGetLastError();
 }
 
+template <int FC, int P, int G>
+static hipError_t set_lds_limit() {
+    const int sh = (int)lds_bytes<FC, P, G>();
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C64, G>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16F, G>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16BF, G>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, sh);
+}
+
+// Variants: FC = frames per workgroup (power of two), P = row pitch, G = groups.
+// FC * (P - 1) <= 2048 keeps the prefetch at <= 8 float4 per thread and the
+// frame stride inside the 16-bit LDS immediate offset.
+#define DAS_VARIANTS(X)                                                                              \
+    X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
+    X(8, 129, 1) X(8, 257, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
+    X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1)
+
+Variant choose_variant(int frames, int max_window) {
+    const int fc = frames >= 32 ? 32 : frames > 8 ? 16 : frames > 4 ? 8 : frames > 2 ? 4 : frames > 1 ? 2 : 1;
+    Variant best{0, 0, 0};
+#define DAS_PICK(FC_, P_, G_)                                                                  \
+    if (FC_ == fc) {                                                                           \
+        if (best.fc == 0 || (best.pitch - 1 < max_window && P_ > best.pitch)) best = {FC_, P_, G_}; \
+    }
+    DAS_VARIANTS(DAS_PICK)
+#undef DAS_PICK
+    return best;
+}
+
+hipError_t prepare_variant(const PlanDev& p) {
+#define DAS_LIMIT(FC_, P_, G_) \
+    if (p.fc == FC_ && p.pitch == P_ && p.groups == G_) return set_lds_limit<FC_, P_, G_>();
+    DAS_VARIANTS(DAS_LIMIT)
+#undef DAS_LIMIT
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_das(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
     if (p.kp.n_tiles == 0) return hipSuccess;
-    const int F = p.kp.F;
-    // LDS per workgroup: FC * P * 16 bytes (~33 KiB for every variant).
-    if (F >= 32) return launch_fc<32, 65>(p, iq, dtype, out, s);
-    if (F > 8) return launch_fc<16, 129>(p, iq, dtype, out, s);
-    if (F > 4) return launch_fc<8, 257>(p, iq, dtype, out, s);
-    if (F > 2) return launch_fc<4, 513>(p, iq, dtype, out, s);
-    if (F > 1) return launch_fc<2, 1025>(p, iq, dtype, out, s);
-    return launch_fc<1, 2049>(p, iq, dtype, out, s);
+#define DAS_LAUNCH(FC_, P_, G_) \
+    if (p.fc == FC_ && p.pitch == P_ && p.groups == G_) return launch_v<FC_, P_, G_>(p, iq, dtype, out, s);
+    DAS_VARIANTS(DAS_LAUNCH)
+#undef DAS_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------- plane-wave arrival table

@@ -58,7 +58,7 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: the argument checks fail f
     (dict(sound_speed=float("nan")), _lib.DAS_EINVAL), (dict(fs=-1.0), _lib.DAS_EINVAL),
     (dict(f_demod=-1.0), _lib.DAS_EINVAL), (dict(t0=float("inf")), _lib.DAS_EINVAL),
     (dict(f_number=-0.5), _lib.DAS_EINVAL), (dict(tukey_alpha=1.5), _lib.DAS_EINVAL),
-    (dict(n_vox=2**31), _lib.DAS_ESHAPE),
+    (dict(n_vox=2**31), _lib.DAS_ESHAPE), (dict(n_samples=2**24, n_frames=32), _lib.DAS_ESHAPE),
 ])
 def test_plan_create_rejects_bad_params(kw, status):
     lib = _lib.load()
