@@ -24,18 +24,19 @@ struct das_rx {
 // Per (voxel, element, transmit): what the multiply-accumulate needs.
 struct das_coef {
     int i0;        // floor(u), valid when active
+    int row;       // i0 - first row of the item's window (set by the caller)
     float beta;    // u - floor(u)
     float cr, ci;  // w * exp(+j 2 pi fd tau)
     bool active;   // w > 0 and -1 <= i0 <= S - 1
 };
 
-// Tukey window on the normalised lateral distance rho (0 outside rho < 1).
-// The taper cos(pi x) uses the hardware cosine, whose argument is in turns.
+// Tukey window on the normalised lateral distance rho (0 outside rho < 1),
+// branch-free.  The taper cos(pi x) uses the hardware cosine (turns).
 __device__ __forceinline__ float das_tukey(float rho, float alpha, float inv_2alpha) {
-    if (!(rho < 1.0f)) return 0.0f;
     const float edge = 1.0f - alpha;
-    if (rho <= edge) return 1.0f;
-    return 0.5f + 0.5f * __builtin_amdgcn_cosf((rho - edge) * inv_2alpha);
+    const float taper = 0.5f + 0.5f * __builtin_amdgcn_cosf((rho - edge) * inv_2alpha);
+    const float w = (rho <= edge) ? 1.0f : taper;
+    return (rho < 1.0f) ? w : 0.0f;
 }
 
 __device__ __forceinline__ das_rx das_rx_setup(float vx, float vy, float vz, float ex, float ey, float ez,
@@ -44,16 +45,17 @@ __device__ __forceinline__ das_rx das_rx_setup(float vx, float vy, float vz, flo
     const double dy = (double)vy - (double)ey;
     const double dz = (double)vz - (double)ez;
     das_rx o;
-    o.r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (!kp.use_apod) {
-        o.w = 1.0f;
-    } else if (!(dz > 0.0)) {
-        o.w = 0.0f;
-    } else {
-        const float lat = sqrtf((float)(dx * dx + dy * dy));
-        const float rho = kp.two_fnum * lat * __builtin_amdgcn_rcpf((float)dz);
-        o.w = das_tukey(rho, kp.alpha, kp.inv_2alpha);
-    }
+    // |x_v - p_e| to ~1e-15 relative: FP32 square root refined by one FP64
+    // Newton step (r + (r2 - r^2) / 2r), cheaper than the FP64 square root.
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const float rf = __builtin_amdgcn_sqrtf((float)r2);
+    const double r0 = (double)rf;
+    o.r = (rf > 0.0f) ? fma(r2 - r0 * r0, (double)(0.5f * __builtin_amdgcn_rcpf(rf)), r0) : 0.0;
+    const float dzf = (float)dz;
+    const float lat = __builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy));
+    const float rho = kp.two_fnum * lat * __builtin_amdgcn_rcpf(dzf);
+    const float wa = (dzf > 0.0f) ? das_tukey(rho, kp.alpha, kp.inv_2alpha) : 0.0f;
+    o.w = kp.use_apod ? wa : 1.0f;
     return o;
 }
 

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 
 #include "das.h"
 #include "das_device.h"
@@ -164,8 +166,18 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 //   coefficients of item k (FP64), then FC frames of one LDS read + six FMAs
 // Fill: thread -> (frame group of FPT frames, run of RPT rows); it loads RPT + 1
 // rows of its frames (each sample once) with 16-byte loads when aligned.
+// Waves per SIMD that the LDS footprint allows (the compiler may then spend
+// registers on instruction-level parallelism instead of occupancy).
+template <int FC, int P, int G>
+constexpr int das_waves_per_simd() {
+    constexpr int bytes = G * 2 * FC * P * 16;
+    constexpr int wgs = (160 * 1024) / bytes;
+    return (wgs * G) < 1 ? 1 : ((wgs * G) > 8 ? 8 : wgs * G);
+}
+
 template <int FC, int P, int DT, int G>
-__global__ __launch_bounds__(kSlots* G) void das_kernel(PlanDev p, const void* __restrict__ iq,
+__global__ __launch_bounds__(kSlots* G) __attribute__((amdgpu_waves_per_eu(das_waves_per_simd<FC, P, G>(), das_waves_per_simd<FC, P, G>())))
+void das_kernel(PlanDev p, const void* __restrict__ iq,
                                                        float2* __restrict__ out, int vec) {
     constexpr int kRows = P - 1;
     constexpr int kBuf = FC * P;  // float4 per buffer
@@ -215,30 +227,32 @@ __global__ __launch_bounds__(kSlots* G) void das_kernel(PlanDev p, const void* _
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
         const int off0 = it.z * row_bytes + lane_off;
-        if (row0 < it.w && fill_frames) {
+        if (row0 < it.w && full_frames) {
 #pragma unroll
             for (int j = 0; j <= RPT; ++j) {
                 const int off = off0 + j * row_bytes;
-                if (full_frames) {
-                    if constexpr (sizeof(Raw) == 16) {
-                        raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-                    } else if constexpr (sizeof(Raw) == 8) {
-                        raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-                    } else {
-                        raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-                    }
+                if constexpr (sizeof(Raw) == 16) {
+                    raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+                } else if constexpr (sizeof(Raw) == 8) {
+                    raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
                 } else {
-                    // unaligned rows or the last partial frame group: one sample at a time
-                    uint32_t* w = reinterpret_cast<uint32_t*>(&raw[j]);
+                    raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                }
+            }
+        } else if (row0 < it.w && fill_frames) {
+            // unaligned rows or the last partial frame group: one sample at a time
 #pragma unroll
-                    for (int q = 0; q < FPT; ++q) {
-                        if (kEB == 8) {
-                            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + q * 8, 0, 0);
-                            w[2 * q] = (uint32_t)v[0];
-                            w[2 * q + 1] = (uint32_t)v[1];
-                        } else {
-                            w[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + q * 4, 0, 0);
-                        }
+            for (int j = 0; j <= RPT; ++j) {
+                const int off = off0 + j * row_bytes;
+                uint32_t* w = reinterpret_cast<uint32_t*>(&raw[j]);
+#pragma unroll
+                for (int q = 0; q < FPT; ++q) {
+                    if (kEB == 8) {
+                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + q * 8, 0, 0);
+                        w[2 * q] = (uint32_t)v[0];
+                        w[2 * q + 1] = (uint32_t)v[1];
+                    } else {
+                        w[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + q * 4, 0, 0);
                     }
                 }
             }
@@ -258,70 +272,86 @@ __global__ __launch_bounds__(kSlots* G) void das_kernel(PlanDev p, const void* _
             }
         }
     };
+    // Coefficients of an item for this lane; lanes outside the aperture, the
+    // record or the item's window get zero weights and row 0 (so the MAC runs
+    // without branches and adds exact zeros).
     int last_e = -1;
     das_rx rx;
-    auto compute_item = [&](const int4& it, float txv, const float4* buf) {
+    auto coef_item = [&](const int4& it, float txv, bool live) {
         if (it.y != last_e) {
             rx = das_rx_setup(vx, vy, vz, p.elem[3 * it.y], p.elem[3 * it.y + 1], p.elem[3 * it.y + 2], kp);
             last_e = it.y;
         }
-        const das_coef c = das_tx_setup(rx, txv, kp);
-        if (vox >= 0 && c.active && c.i0 >= it.z && c.i0 < it.z + it.w) {
-            const float4* src = buf + (c.i0 - it.z);
+        das_coef c = das_tx_setup(rx, txv, kp);
+        const bool use = live && (vox >= 0) && c.active && c.i0 >= it.z && c.i0 < it.z + it.w;
+        c.row = use ? c.i0 - it.z : 0;
+        c.beta = use ? c.beta : 0.0f;
+        c.cr = use ? c.cr : 0.0f;
+        c.ci = use ? c.ci : 0.0f;
+        return c;
+    };
+    auto mac_item = [&](const das_coef& c, const float4* buf) {
+        const float4* src = buf + c.row;
 #pragma unroll
-            for (int f = 0; f < FC; ++f) {
-                const float4 d = src[((f % FPT) * NFG + f / FPT) * P];
-                const float tr = fmaf(c.beta, d.z, d.x);
-                const float ti = fmaf(c.beta, d.w, d.y);
-                acc_r[f] = fmaf(c.cr, tr, acc_r[f]);
-                acc_r[f] = fmaf(-c.ci, ti, acc_r[f]);
-                acc_i[f] = fmaf(c.cr, ti, acc_i[f]);
-                acc_i[f] = fmaf(c.ci, tr, acc_i[f]);
-            }
+        for (int f = 0; f < FC; ++f) {
+            const float4 d = src[((f % FPT) * NFG + f / FPT) * P];
+            const float tr = fmaf(c.beta, d.z, d.x);
+            const float ti = fmaf(c.beta, d.w, d.y);
+            acc_r[f] = fmaf(c.cr, tr, acc_r[f]);
+            acc_r[f] = fmaf(-c.ci, ti, acc_r[f]);
+            acc_i[f] = fmaf(c.cr, ti, acc_i[f]);
+            acc_i[f] = fmaf(c.ci, tr, acc_i[f]);
         }
     };
 
+    // Step s of this group handles item k_s = s * G + grp.  Registers of stage
+    // s % 2 hold the window, transmit time and item of k_s (loaded at step
+    // s - 2); coefficients of k_s were formed during step s - 1.
+    // Both window buffers start zeroed, so a step without an item (its
+    // coefficients are zero) multiplies zeros, never stale or unset LDS.
+    for (int i = gt; i < 2 * kBuf; i += kSlots) buf0[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    __syncthreads();
     Raw ra[RPT + 1], rb[RPT + 1];
     float txa = 0.0f, txb = 0.0f;
     int4 ita = make_int4(0, 0, 0, 0), itb = make_int4(0, 0, 0, 0);
     if (grp < nitems) load_item(grp, ra, txa, ita);
     if (grp + G < nitems) load_item(grp + G, rb, txb, itb);
+    das_coef cc = coef_item(ita, txa, grp < nitems);
     for (int step = 0; step < nsteps; step += 2) {
         {
             const int k = step * G + grp;
-            const bool have = k < nitems;
-            const int4 it = ita;
-            if (have) store_item(it, ra, buf0);
+            if (k < nitems) store_item(ita, ra, buf0);
             __syncthreads();
-            const float txc = txa;
             if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa, ita);
-            if (have) compute_item(it, txc, buf0);
+            const das_coef cn = coef_item(itb, txb, k + G < nitems);  // item k + G
+            mac_item(cc, buf0);
+            cc = cn;
         }
         if (step + 1 < nsteps) {
             const int k = (step + 1) * G + grp;
-            const bool have = k < nitems;
-            const int4 it = itb;
-            if (have) store_item(it, rb, buf1);
+            if (k < nitems) store_item(itb, rb, buf1);
             __syncthreads();
-            const float txc = txb;
             if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb, itb);
-            if (have) compute_item(it, txc, buf1);
+            const das_coef cn = coef_item(ita, txa, k + G < nitems);  // item k + G
+            mac_item(cc, buf1);
+            cc = cn;
         }
     }
     if (G > 1) {
-        // fixed-order reduction of the groups' partial sums through LDS
-        float2* red = reinterpret_cast<float2*>(lds);  // [G-1][FC][kSlots]
-        __syncthreads();
-        if (grp > 0) {
+        // Fixed-order reduction of the groups' partial sums through LDS:
+        // ((g0 + g1) + g2) + ...
+        float2* red = reinterpret_cast<float2*>(lds);  // [FC][kSlots]
+        for (int g = 1; g < G; ++g) {
+            __syncthreads();
+            if (grp == g) {
 #pragma unroll
-            for (int f = 0; f < FC; ++f) red[((grp - 1) * FC + f) * kSlots + gt] = make_float2(acc_r[f], acc_i[f]);
-        }
-        __syncthreads();
-        if (grp == 0) {
-            for (int g = 1; g < G; ++g) {
+                for (int f = 0; f < FC; ++f) red[f * kSlots + gt] = make_float2(acc_r[f], acc_i[f]);
+            }
+            __syncthreads();
+            if (grp == 0) {
 #pragma unroll
                 for (int f = 0; f < FC; ++f) {
-                    const float2 v = red[((g - 1) * FC + f) * kSlots + gt];
+                    const float2 v = red[f * kSlots + gt];
                     acc_r[f] += v.x;
                     acc_i[f] += v.y;
                 }
@@ -339,7 +369,7 @@ __global__ __launch_bounds__(kSlots* G) void das_kernel(PlanDev p, const void* _
 template <int FC, int P, int G>
 static size_t lds_bytes() {
     const size_t win = (size_t)G * 2 * FC * P * sizeof(float4);
-    const size_t red = (size_t)(G - 1) * FC * kSlots * sizeof(float2);
+    const size_t red = (size_t)(G > 1 ? 1 : 0) * FC * kSlots * sizeof(float2);
     return win > red ? win : red;
 }
 
@@ -392,15 +422,28 @@ static hipError_t set_lds_limit() {
 // FC * (P - 1) <= 2048 keeps the prefetch at <= 8 float4 per thread and the
 // frame stride inside the 16-bit LDS immediate offset.
 #define DAS_VARIANTS(X)                                                                              \
-    X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
+    X(32, 41, 3) X(32, 49, 3) X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
     X(8, 129, 1) X(8, 257, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
     X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1)
 
 Variant choose_variant(int frames, int max_window) {
     const int fc = frames >= 32 ? 32 : frames > 8 ? 16 : frames > 4 ? 8 : frames > 2 ? 4 : frames > 1 ? 2 : 1;
+    if (const char* env = std::getenv("DAS_VARIANT")) {  // tuning override: "fc,pitch,groups"
+        int f = 0, pp = 0, g = 0;
+        if (std::sscanf(env, "%d,%d,%d", &f, &pp, &g) == 3 && f == fc) {
+#define DAS_FIND(FC_, P_, G_) \
+    if (FC_ == f && P_ == pp && G_ == g) return Variant{FC_, P_, G_};
+            DAS_VARIANTS(DAS_FIND)
+#undef DAS_FIND
+        }
+    }
+    // More groups (more waves per SIMD) when the tile windows fit a short pitch;
+    // otherwise the smallest pitch that holds the largest window in one piece.
+    if (fc == 32 && max_window <= 40) return Variant{32, 41, 3};
+    if (fc == 32 && max_window <= 48) return Variant{32, 49, 3};
     Variant best{0, 0, 0};
 #define DAS_PICK(FC_, P_, G_)                                                                  \
-    if (FC_ == fc) {                                                                           \
+    if (FC_ == fc && (G_ <= 2)) {                                                              \
         if (best.fc == 0 || (best.pitch - 1 < max_window && P_ > best.pitch)) best = {FC_, P_, G_}; \
     }
     DAS_VARIANTS(DAS_PICK)
