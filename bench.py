@@ -169,10 +169,11 @@ def main():
         "active_points_per_s": active_pts / (ms * 1e-3),
         "active_fraction": info["active_triples"] / max(1, info["total_triples"]),
         "processed_fraction": info["processed_triples"] / max(1, info["total_triples"]),
-        "plan": {"tiles": info["n_tiles"], "tile_dims": info["tile_dims"], "max_window": info["max_window"]},
+        "plan": {"tiles": info["n_tiles"], "tile_dims": info["tile_dims"], "max_window": info["max_window"],
+                 "kernel": "das_kernel<fc=%d, pitch=%d, groups=%d>" % info["kernel"]},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "das_kernel<32,65,c64>",
+                     "kernel": "das_kernel<fc=%d, pitch=%d, complex64, groups=%d>" % info["kernel"],
                      "work": "%d FLOP x active points (w > 0, inside the record) per launch" % FLOP_PER_POINT},
         "paper_context": {"points_per_s": PAPER_PTS_PER_S, "hardware": "NVIDIA GeForce RTX 5090",
                           "workload": "PyMUST rotating disk 251 x 251, 32 frames"},

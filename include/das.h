@@ -145,6 +145,9 @@ typedef struct das_plan_info {
     int32_t tile_dims[3];      /* lattice points per tile along x, y, z (0 when
                                   the points are not a lattice)                */
     int32_t max_window;        /* largest per-tile sample window (rows)        */
+    int32_t kernel_fc;         /* kernel variant: frames per workgroup,        */
+    int32_t kernel_pitch;      /*   LDS row pitch (window rows + 1),           */
+    int32_t kernel_groups;     /*   element groups of 4 waves per tile         */
 } das_plan_info;
 
 /* Fill `info` (host) for `plan`.  Host-only, synchronous. */
@@ -173,7 +176,7 @@ const char *das_status_string(int status);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *das_last_error(void);
 
-/* ABI version: (major << 16) | minor. */
+/* ABI version: (major << 16) | minor (this header: 1.1). */
 int das_version(void);
 
 #ifdef __cplusplus

@@ -38,7 +38,8 @@ class DasPlanInfo(ctypes.Structure):
     _fields_ = [("n_vox", ctypes.c_int64), ("n_slots", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
                 ("total_triples", ctypes.c_int64), ("active_triples", ctypes.c_int64),
                 ("processed_triples", ctypes.c_int64), ("tile_dims", ctypes.c_int32 * 3),
-                ("max_window", ctypes.c_int32)]
+                ("max_window", ctypes.c_int32), ("kernel_fc", ctypes.c_int32), ("kernel_pitch", ctypes.c_int32),
+                ("kernel_groups", ctypes.c_int32)]
 
 
 _lib = None

@@ -251,7 +251,7 @@ static hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 extern "C" {
 
-int das_version(void) { return (1 << 16) | 0; }
+int das_version(void) { return (1 << 16) | 1; }
 
 const char* das_last_error(void) { return g_err.c_str(); }
 
@@ -479,6 +479,9 @@ int das_plan_query(const das_plan* plan, das_plan_info* info) {
     info->processed_triples = plan->processed_triples;
     for (int a = 0; a < 3; ++a) info->tile_dims[a] = plan->tiling.tile_dims[a];
     info->max_window = plan->max_window;
+    info->kernel_fc = plan->dev.fc;
+    info->kernel_pitch = plan->dev.pitch;
+    info->kernel_groups = plan->dev.groups;
     return DAS_OK;
 }
 

@@ -93,7 +93,8 @@ class Plan:
         return {"n_vox": inf.n_vox, "n_slots": inf.n_slots, "n_tiles": inf.n_tiles,
                 "total_triples": inf.total_triples, "active_triples": inf.active_triples,
                 "processed_triples": inf.processed_triples, "tile_dims": tuple(inf.tile_dims),
-                "max_window": inf.max_window}
+                "max_window": inf.max_window,
+                "kernel": (inf.kernel_fc, inf.kernel_pitch, inf.kernel_groups)}
 
     def execute(self, iq, out=None, stream=None):
         """Beamform ``iq`` into ``out`` (complex64 [V, F], allocated if None)."""
