@@ -235,7 +235,7 @@ static bool plan_live(const das_plan* plan) {
 }
 
 static void free_dev(das::PlanDev& d) {
-    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows, d.items, d.item_off};
+    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows, d.items, d.item_off, d.wg_tile};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = das::PlanDev();
@@ -309,7 +309,7 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
     }
     const das::Tiling& tl = plan->tiling;
     const int64_t n_slots = tl.n_tiles * das::kSlots;
-    if (tl.n_tiles > (int64_t)INT32_MAX / das::kSlots) {
+    if (tl.n_tiles > (int64_t)INT32_MAX / das::kSlots || tl.n_tiles * (int64_t)p->n_frames > (int64_t)INT32_MAX) {
         delete plan;
         return fail(DAS_ESHAPE, "too many tiles");
     }
@@ -369,7 +369,7 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
         // Work items per tile: the non-empty (t, e) windows, cut into pieces of at
         // most pitch - 1 rows, element-major so consecutive items share the
         // receive geometry.
-        const das::Variant var = das::choose_variant(p->n_frames, plan->max_window);
+        const das::Variant var = das::choose_variant(p->n_frames, plan->max_window, tl.n_tiles);
         d.fc = var.fc;
         d.pitch = var.pitch;
         d.groups = var.groups;
@@ -394,9 +394,27 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
             }
         }
         off[tl.n_tiles] = (int32_t)items.size();
+        // Workgroups are dispatched in index order, so handing out tiles heaviest
+        // first (by work items, i.e. multiply-accumulate passes) balances the CUs
+        // greedily; DAS_ORDER=xcd gives each XCD a contiguous run of tiles instead.
+        std::vector<int32_t> order((size_t)tl.n_tiles);
+        std::iota(order.begin(), order.end(), 0);
+        const char* ord = std::getenv("DAS_ORDER");
+        if (ord && std::strcmp(ord, "xcd") == 0) {
+            const int64_t n = tl.n_tiles, q = n / 8, r = n % 8;
+            for (int64_t b = 0; b < n; ++b) {
+                const int64_t x = b % 8, kk = b / 8;
+                order[b] = (int32_t)(x < r ? x * (q + 1) + kk : r * (q + 1) + (x - r) * q + kk);
+            }
+        } else {
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                return off[a + 1] - off[a] > off[b + 1] - off[b];
+            });
+        }
         (void)hipFree(d.windows);
         d.windows = nullptr;
-        if ((e = upload(&d.items, items, s)) != hipSuccess || (e = upload(&d.item_off, off, s)) != hipSuccess)
+        if ((e = upload(&d.items, items, s)) != hipSuccess || (e = upload(&d.item_off, off, s)) != hipSuccess ||
+            (e = upload(&d.wg_tile, order, s)) != hipSuccess)
             goto hip_fail;
         if ((e = das::prepare_variant(d)) != hipSuccess) goto hip_fail;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) goto hip_fail;

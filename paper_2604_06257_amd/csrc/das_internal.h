@@ -39,6 +39,7 @@ struct PlanDev {
     int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows); plan-time only
     int4* items = nullptr;      // per tile, the (t, e, first row, rows) work items, e-major
     int32_t* item_off = nullptr;  // [n_tiles + 1] offsets into items
+    int32_t* wg_tile = nullptr;   // [n_tiles] workgroup -> tile, heaviest tiles first
     int32_t fc = 0, pitch = 0, groups = 1;  // kernel variant: frames per workgroup, LDS row pitch, element groups
 };
 
@@ -46,7 +47,7 @@ struct PlanDev {
 struct Variant {
     int fc, pitch, groups;
 };
-Variant choose_variant(int frames, int max_window);
+Variant choose_variant(int frames, int max_window, int64_t n_tiles);
 
 // Computes per (tile, transmit, element) sample windows and counts.
 // counts[0] = active (slot, e, t) triples (w > 0, inside the record);

@@ -74,15 +74,6 @@ __device__ __forceinline__ float2 decode(const R& raw, int j) {
     }
 }
 
-// Workgroup id -> tile so that each XCD (workgroups are dispatched round-robin
-// over the 8 XCDs) works on one contiguous run of tiles: neighbouring tiles
-// share channel-data windows, which then stay in that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int bid, int n) {
-    const int q = n >> 3, r = n & 7;
-    const int xcd = bid & 7, k = bid >> 3;
-    return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
-}
-
 // ------------------------------------------------------- window pre-pass
 // For every (tile, t, e): first and last sample row used by any active lane.
 __global__ __launch_bounds__(kSlots) void window_kernel(PlanDev p, unsigned long long* counts) {
@@ -188,8 +179,10 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
     using Raw = typename RawT<FPT * kEB>::type;
     extern __shared__ float4 lds[];  // [G][2][FC][P]
     const das_kparams& kp = p.kp;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int f0 = blockIdx.y * FC;
+    // workgroup -> (tile, frame chunk): all chunks of the heaviest tiles are dispatched first
+    const int nchunk = (p.kp.F + FC - 1) / FC;
+    const int tile = p.wg_tile[blockIdx.x / nchunk];
+    const int f0 = (blockIdx.x % nchunk) * FC;
     // group index is wave-uniform (a group is 4 whole waves); say so to the compiler
     const int grp = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kSlots));
     const int gt = threadIdx.x % kSlots;  // slot within the tile
@@ -383,7 +376,7 @@ static int vec_loads_ok(const PlanDev& p, const void* iq) {
 
 template <int FC, int P, int G>
 static hipError_t launch_v(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
-    const dim3 grid(p.kp.n_tiles, (p.kp.F + FC - 1) / FC);
+    const dim3 grid((unsigned)(p.kp.n_tiles * ((p.kp.F + FC - 1) / FC)));
     const dim3 block(kSlots * G);
     const size_t sh = lds_bytes<FC, P, G>();
     float2* o = reinterpret_cast<float2*>(out);
@@ -423,22 +416,31 @@ static hipError_t set_lds_limit() {
 // frame stride inside the 16-bit LDS immediate offset.
 #define DAS_VARIANTS(X)                                                                              \
     X(32, 41, 3) X(32, 49, 3) X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
-    X(8, 129, 1) X(8, 257, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
-    X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1)
+    X(8, 129, 1) X(8, 257, 1) X(4, 33, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
+    X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 65, 1) X(1, 129, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1)
 
-Variant choose_variant(int frames, int max_window) {
-    const int fc = frames >= 32 ? 32 : frames > 8 ? 16 : frames > 4 ? 8 : frames > 2 ? 4 : frames > 1 ? 2 : 1;
+// Variant choice (measured on MI355X with the c1 / c2 / c3 workloads):
+//  - frames are cut into chunks of FC; more chunks mean more workgroups, which
+//    the heaviest-first dispatch order balances, at the cost of forming the
+//    coefficients once per chunk;
+//  - the LDS pitch is the smallest that holds the largest tile window in one
+//    piece (a split window costs a whole extra multiply-accumulate pass);
+//  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks.
+Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
+    int fc;
+    if (frames >= 32) fc = (n_tiles < 512) ? 16 : 32;
+    else if (frames > 8) fc = 16;
+    else if (frames > 4) fc = 4;
+    else fc = frames > 2 ? 4 : frames > 1 ? 2 : 1;
     if (const char* env = std::getenv("DAS_VARIANT")) {  // tuning override: "fc,pitch,groups"
         int f = 0, pp = 0, g = 0;
-        if (std::sscanf(env, "%d,%d,%d", &f, &pp, &g) == 3 && f == fc) {
+        if (std::sscanf(env, "%d,%d,%d", &f, &pp, &g) == 3 && f <= (frames >= 32 ? 32 : fc * 2)) {
 #define DAS_FIND(FC_, P_, G_) \
     if (FC_ == f && P_ == pp && G_ == g) return Variant{FC_, P_, G_};
             DAS_VARIANTS(DAS_FIND)
 #undef DAS_FIND
         }
     }
-    // More groups (more waves per SIMD) when the tile windows fit a short pitch;
-    // otherwise the smallest pitch that holds the largest window in one piece.
     if (fc == 32 && max_window <= 40) return Variant{32, 41, 3};
     if (fc == 32 && max_window <= 48) return Variant{32, 49, 3};
     Variant best{0, 0, 0};
