@@ -35,6 +35,31 @@ WORKLOADS = {
 FLOP_PER_POINT = 16          # two complex multiply-accumulates per (voxel, element, transmit, frame)
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
 PAPER_PTS_PER_S = 258052096 / 0.23e-3   # RTX 5090, 251 x 251 rotating disk (context only)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "das_kernel_traffic.txt")
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_06257_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch recorded by rocprofv3 for the current kernel sources, else None."""
+    try:
+        lines = [l.split() for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith("#")]
+    except OSError:
+        return None
+    rec = {l[0]: l[1:] for l in lines}
+    if rec.get("source_sha256", [None])[0] != kernel_source_hash() or workload not in rec:
+        return None
+    f = dict(zip(rec[workload][::2], rec[workload][1::2]))
+    return int(f["read_bytes"]) + int(f["write_bytes"])
 
 
 def _cores():
@@ -172,7 +197,7 @@ def main():
         "plan": {"tiles": info["n_tiles"], "tile_dims": info["tile_dims"], "max_window": info["max_window"],
                  "kernel": "das_kernel<fc=%d, pitch=%d, groups=%d>" % info["kernel"]},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "das_kernel<fc=%d, pitch=%d, complex64, groups=%d>" % info["kernel"],
                      "work": "%d FLOP x active points (w > 0, inside the record) per launch" % FLOP_PER_POINT},
         "paper_context": {"points_per_s": PAPER_PTS_PER_S, "hardware": "NVIDIA GeForce RTX 5090",

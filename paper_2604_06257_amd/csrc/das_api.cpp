@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <numeric>
 #include <string>
 #include <unordered_set>
@@ -170,6 +171,9 @@ int tile_points(const float* xyz, int64_t n, const char* spec, Tiling& out, std:
                     }
                     if (any) {
                         out.slot_to_vox.insert(out.slot_to_vox.end(), slots.begin(), slots.end());
+                        out.tile_xyz.push_back((int32_t)bx);
+                        out.tile_xyz.push_back((int32_t)by);
+                        out.tile_xyz.push_back((int32_t)bz);
                         ++out.n_tiles;
                     }
                 }
@@ -200,8 +204,63 @@ int tile_points(const float* xyz, int64_t n, const char* spec, Tiling& out, std:
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
     out.n_tiles = (n + kSlots - 1) / kSlots;
     out.slot_to_vox.assign(out.n_tiles * kSlots, -1);
+    for (int64_t t = 0; t < out.n_tiles; ++t) {
+        out.tile_xyz.push_back((int32_t)t);
+        out.tile_xyz.push_back(0);
+        out.tile_xyz.push_back(0);
+    }
     std::copy(order.begin(), order.end(), out.slot_to_vox.begin());
     return DAS_OK;
+}
+
+}  // namespace das
+
+namespace das {
+
+std::vector<int32_t> order_units(const Tiling& tl, const std::vector<int32_t>& item_off, int chunks, bool xcd_runs) {
+    const int64_t n = tl.n_tiles;
+    std::vector<int32_t> units;
+    units.reserve((size_t)(n * chunks));
+    auto cost = [&](int32_t t) { return item_off[t + 1] - item_off[t]; };
+    if (xcd_runs) {  // contiguous runs of tiles per XCD (kept for comparison)
+        const int64_t q = n / 8, r = n % 8;
+        for (int64_t b = 0; b < n; ++b) {
+            const int64_t x = b % 8, kk = b / 8;
+            const int32_t t = (int32_t)(x < r ? x * (q + 1) + kk : r * (q + 1) + (x - r) * q + kk);
+            for (int c = 0; c < chunks; ++c) units.push_back(t * chunks + c);
+        }
+        return units;
+    }
+    // columns = tiles sharing (x, y) tile coordinates; in row-major (y, x) order
+    std::vector<int32_t> idx((size_t)n);
+    std::iota(idx.begin(), idx.end(), 0);
+    auto col_key = [&](int32_t t) { return std::make_pair(tl.tile_xyz[3 * t + 1], tl.tile_xyz[3 * t]); };
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return col_key(a) < col_key(b); });
+    int64_t total = 0;
+    for (int32_t t : idx) total += cost(t);
+    // split the column sequence into 8 regions of about equal work (whole columns)
+    std::vector<std::vector<int32_t>> region(8);
+    int64_t acc = 0;
+    int r = 0;
+    for (size_t i = 0; i < idx.size();) {
+        size_t j = i;
+        int64_t col_cost = 0;
+        while (j < idx.size() && col_key(idx[j]) == col_key(idx[i])) col_cost += cost(idx[j++]);
+        if (r < 7 && acc > 0 && acc + col_cost / 2 > (total * (r + 1)) / 8) ++r;
+        for (size_t k = i; k < j; ++k) region[r].push_back(idx[k]);
+        acc += col_cost;
+        i = j;
+    }
+    size_t longest = 0;
+    for (auto& g : region) {
+        std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) { return cost(a) > cost(b); });
+        longest = std::max(longest, g.size() * (size_t)chunks);
+    }
+    for (size_t k = 0; k < longest; ++k)
+        for (int x = 0; x < 8; ++x)
+            if (k < region[x].size() * (size_t)chunks)
+                units.push_back(region[x][k / chunks] * chunks + (int32_t)(k % chunks));
+    return units;
 }
 
 }  // namespace das
@@ -235,7 +294,7 @@ static bool plan_live(const das_plan* plan) {
 }
 
 static void free_dev(das::PlanDev& d) {
-    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows, d.items, d.item_off, d.wg_tile};
+    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows, d.items, d.item_off, d.wg_unit};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = das::PlanDev();
@@ -394,27 +453,14 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
             }
         }
         off[tl.n_tiles] = (int32_t)items.size();
-        // Workgroups are dispatched in index order, so handing out tiles heaviest
-        // first (by work items, i.e. multiply-accumulate passes) balances the CUs
-        // greedily; DAS_ORDER=xcd gives each XCD a contiguous run of tiles instead.
-        std::vector<int32_t> order((size_t)tl.n_tiles);
-        std::iota(order.begin(), order.end(), 0);
+        const int chunks = (p->n_frames + var.fc - 1) / var.fc;
         const char* ord = std::getenv("DAS_ORDER");
-        if (ord && std::strcmp(ord, "xcd") == 0) {
-            const int64_t n = tl.n_tiles, q = n / 8, r = n % 8;
-            for (int64_t b = 0; b < n; ++b) {
-                const int64_t x = b % 8, kk = b / 8;
-                order[b] = (int32_t)(x < r ? x * (q + 1) + kk : r * (q + 1) + (x - r) * q + kk);
-            }
-        } else {
-            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-                return off[a + 1] - off[a] > off[b + 1] - off[b];
-            });
-        }
+        const std::vector<int32_t> order =
+            das::order_units(tl, off, chunks, ord != nullptr && std::strcmp(ord, "xcd") == 0);
         (void)hipFree(d.windows);
         d.windows = nullptr;
         if ((e = upload(&d.items, items, s)) != hipSuccess || (e = upload(&d.item_off, off, s)) != hipSuccess ||
-            (e = upload(&d.wg_tile, order, s)) != hipSuccess)
+            (e = upload(&d.wg_unit, order, s)) != hipSuccess)
             goto hip_fail;
         if ((e = das::prepare_variant(d)) != hipSuccess) goto hip_fail;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) goto hip_fail;

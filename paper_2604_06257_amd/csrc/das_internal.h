@@ -23,6 +23,7 @@ struct Tiling {
     int32_t wave_dims[3] = {0, 0, 0};   // lattice points per wave
     int64_t n_tiles = 0;
     std::vector<int32_t> slot_to_vox;   // n_tiles * kSlots
+    std::vector<int32_t> tile_xyz;      // n_tiles * 3 tile coordinates (lattice), else (index, 0, 0)
 };
 
 // Returns 0 or a negative das_status; err receives a message.
@@ -39,9 +40,14 @@ struct PlanDev {
     int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows); plan-time only
     int4* items = nullptr;      // per tile, the (t, e, first row, rows) work items, e-major
     int32_t* item_off = nullptr;  // [n_tiles + 1] offsets into items
-    int32_t* wg_tile = nullptr;   // [n_tiles] workgroup -> tile, heaviest tiles first
+    int32_t* wg_unit = nullptr;   // [n_tiles * chunks] workgroup -> tile * chunks + frame chunk
     int32_t fc = 0, pitch = 0, groups = 1;  // kernel variant: frames per workgroup, LDS row pitch, element groups
 };
+
+// Workgroup -> (tile, frame chunk) order: each of the 8 XCDs gets a lateral
+// region of tile columns (all depths), heaviest units first inside a region,
+// regions interleaved so that workgroup w runs on XCD w % 8.
+std::vector<int32_t> order_units(const Tiling& tl, const std::vector<int32_t>& item_off, int chunks, bool xcd_runs);
 
 // Kernel variant for F frames and the largest tile window (rows).
 struct Variant {

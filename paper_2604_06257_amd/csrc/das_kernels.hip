@@ -181,8 +181,9 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
     const das_kparams& kp = p.kp;
     // workgroup -> (tile, frame chunk): all chunks of the heaviest tiles are dispatched first
     const int nchunk = (p.kp.F + FC - 1) / FC;
-    const int tile = p.wg_tile[blockIdx.x / nchunk];
-    const int f0 = (blockIdx.x % nchunk) * FC;
+    const int unit = p.wg_unit[blockIdx.x];
+    const int tile = unit / nchunk;
+    const int f0 = (unit % nchunk) * FC;
     // group index is wave-uniform (a group is 4 whole waves); say so to the compiler
     const int grp = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kSlots));
     const int gt = threadIdx.x % kSlots;  // slot within the tile
