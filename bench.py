@@ -127,6 +127,46 @@ def time_steps(plan, iq, out, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def scaling_sweep(axis, steps, warmup):
+    """Throughput while one size varies around the rotating-disk stand-in (paper Sec. 4.5, Fig. 5):
+    voxels 63k-6.3M (finer grids over the same region), elements 128-8192 (same aperture), frames 1-512.
+    IQ is seeded circular-Gaussian data generated on the device; one JSON line per point."""
+    import torch
+
+    import paper_2604_06257_amd as das
+    from synth import grid_2d, linear_array
+
+    c, fc = 1540.0, 5e6
+    fs, S = 4 * fc, 2048
+    base = dict(n_side=256, n_elem=128, frames=32)
+    points = {"voxels": [("n_side", n) for n in (251, 502, 1004, 1587, 2510)],
+              "elements": [("n_elem", e) for e in (128, 256, 512, 1024, 2048, 4096, 8192)],
+              "frames": [("frames", f) for f in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512)]}[axis]
+    gen = torch.Generator(device="cuda")
+    for key, val in points:
+        cfg = dict(base)
+        cfg[key] = val
+        n, E, F = cfg["n_side"], cfg["n_elem"], cfg["frames"]
+        xs = np.linspace(-12.8e-3, 12.8e-3, n)
+        zs = np.linspace(10e-3, 35.5e-3, n)
+        vox = torch.from_numpy(grid_2d(xs, zs)).cuda()
+        elem = torch.from_numpy(linear_array(E, 38.4e-3 / E)).cuda()
+        tx = das.tx_plane_wave(vox, np.zeros((1, 2)), c)
+        gen.manual_seed(1000 + val)
+        iq = torch.randn((1, E, S, F), dtype=torch.complex64, device="cuda", generator=gen)
+        params = das.Params(1, E, S, F, vox.shape[0], c, fs, fc, 0.0, 1.0, 0.5)
+        with das.Plan(params, elem, vox, tx) as plan:
+            info = plan.info()
+            out = torch.empty((vox.shape[0], F), dtype=torch.complex64, device="cuda")
+            ms, _ = time_steps(plan, iq, out, steps, warmup, torch)
+        pts = vox.shape[0] * E * F
+        print(json.dumps({"sweep": axis, "voxels": vox.shape[0], "elements": E, "frames": F, "ms_per_step": ms,
+                          "points_per_s": pts / (ms * 1e-3), "active_fraction": info["active_triples"] /
+                          max(1, info["total_triples"]), "kernel": "fc=%d pitch=%d groups=%d" % info["kernel"]}),
+              flush=True)
+        del iq, out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,7 +178,12 @@ def main():
     ap.add_argument("--cpu-voxels", type=int, default=None, help="voxels in the oracle sample (default: all)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a torch copy of this many GiB (for HBM counter calibration)")
+    ap.add_argument("--sweep", choices=("voxels", "elements", "frames"), default=None,
+                    help="print one JSON line per size along this axis instead of the benchmark line")
     args = ap.parse_args()
+    if args.sweep:
+        scaling_sweep(args.sweep, args.steps, args.warmup)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build's path runs on a single MI355X "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
