@@ -39,10 +39,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "das_kernel_traffic.txt")
 
 
 def kernel_source_hash():
+    """SHA-256 over the sources the delay-and-sum kernel is built from (csrc/das_*)."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_06257_amd", "csrc", "*"))):
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_06257_amd", "csrc", "das_*"))):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
