@@ -16,6 +16,13 @@ Architecture (channel counts c0..c3 = 16, 32, 48, 64 by default):
   prediction = base + net[..., :2];  loss = mean((prediction - target)^2)
 The gradients are the analytic backward pass of these definitions; they are
 pinned by finite differences in the tests.
+
+``store`` (default: none) is applied to every tensor at the points where an
+implementation keeps it in memory: each activation and pooled tensor in the
+forward pass, the loss gradient, and each propagated gradient in the backward
+pass (after its ReLU mask).  Passing bfloat16 rounding there gives the exact
+values of a network that stores its tensors in bfloat16 and computes in high
+precision; ``store=None`` is the plain float64 network.
 """
 
 import numpy as np
@@ -78,23 +85,28 @@ def layer_shapes(cin=8, chans=(16, 32, 48, 64), cout=16):
             ("d1b", c1, c1), ("d0a", c0 + c1, c0), ("d0b", c0, c0), ("out", c0, cout)]
 
 
-def forward(params, x):
+def _identity(a):
+    return a
+
+
+def forward(params, x, store=None):
     """params: {name: (w, b)}; x [D,H,W,Cin].  Returns (net [D,H,W,Cout], cache)."""
+    st = store or _identity
     relu = lambda a: np.maximum(a, 0.0)  # noqa: E731
     c = {"x": x}
     h = x
     for l in range(3):
-        c["ea%d" % l] = relu(conv3d(h, *params["e%da" % l]))
-        c["s%d" % l] = relu(conv3d(c["ea%d" % l], *params["e%db" % l]))
-        c["p%d" % l] = avgpool2(c["s%d" % l])
+        c["ea%d" % l] = st(relu(conv3d(h, *params["e%da" % l])))
+        c["s%d" % l] = st(relu(conv3d(c["ea%d" % l], *params["e%db" % l])))
+        c["p%d" % l] = st(avgpool2(c["s%d" % l]))
         h = c["p%d" % l]
-    c["ea3"] = relu(conv3d(h, *params["e3a"]))
-    c["b3"] = relu(conv3d(c["ea3"], *params["e3b"]))
+    c["ea3"] = st(relu(conv3d(h, *params["e3a"])))
+    c["b3"] = st(relu(conv3d(c["ea3"], *params["e3b"])))
     prev = c["b3"]
     for l in (2, 1, 0):
         c["cat%d" % l] = np.concatenate([c["s%d" % l], upsample2(prev)], axis=3)
-        c["da%d" % l] = relu(conv3d(c["cat%d" % l], *params["d%da" % l]))
-        c["db%d" % l] = relu(conv3d(c["da%d" % l], *params["d%db" % l]))
+        c["da%d" % l] = st(relu(conv3d(c["cat%d" % l], *params["d%da" % l])))
+        c["db%d" % l] = st(relu(conv3d(c["da%d" % l], *params["d%db" % l])))
         prev = c["db%d" % l]
     net = conv3d(prev, *params["out"])
     return net, c
@@ -109,28 +121,34 @@ def loss_and_grad_net(net, base, target):
     return float((e ** 2).sum() / n), g
 
 
-def backward(params, cache, gnet):
-    """Analytic gradients {name: (dw, db)} of the network for d loss / d net = gnet."""
+def backward(params, cache, gnet, store=None):
+    """Analytic gradients {name: (dw, db)} of the network for d loss / d net = gnet.
+
+    A propagated gradient is stored after the ReLU mask of the tensor it
+    belongs to; rounding commutes with a 0/1 mask, so store() may be applied
+    before the mask multiplies it."""
+    st = store or _identity
     grads = {}
     relu_mask = lambda a: (a > 0).astype(np.float64)  # noqa: E731
-    g, grads["out"] = _conv_grads(cache["db0"], params["out"], gnet)
+    g, grads["out"] = _conv_grads(cache["db0"], params["out"], st(gnet))
     skip_g = {}
     for l in (0, 1, 2):
-        g = g * relu_mask(cache["db%d" % l])
+        g = st(g) * relu_mask(cache["db%d" % l])
         g, grads["d%db" % l] = _conv_grads(cache["da%d" % l], params["d%db" % l], g)
-        g = g * relu_mask(cache["da%d" % l])
+        g = st(g) * relu_mask(cache["da%d" % l])
         g, grads["d%da" % l] = _conv_grads(cache["cat%d" % l], params["d%da" % l], g)
+        g = st(g * relu_mask(cache["cat%d" % l]))
         cs = cache["s%d" % l].shape[3]
         skip_g[l] = g[..., :cs]
         g = upsample2_backward(g[..., cs:])
-    g = g * relu_mask(cache["b3"])
+    g = st(g) * relu_mask(cache["b3"])
     g, grads["e3b"] = _conv_grads(cache["ea3"], params["e3b"], g)
-    g = g * relu_mask(cache["ea3"])
+    g = st(g) * relu_mask(cache["ea3"])
     g, grads["e3a"] = _conv_grads(cache["p2"], params["e3a"], g)
     for l in (2, 1, 0):
-        g = (skip_g[l] + avgpool2_backward(g)) * relu_mask(cache["s%d" % l])
+        g = st((skip_g[l] + st(avgpool2_backward(st(g)))) * relu_mask(cache["s%d" % l]))
         g, grads["e%db" % l] = _conv_grads(cache["ea%d" % l], params["e%db" % l], g)
-        g = g * relu_mask(cache["ea%d" % l])
+        g = st(g) * relu_mask(cache["ea%d" % l])
         src = cache["p%d" % (l - 1)] if l > 0 else cache["x"]
         g, grads["e%da" % l] = _conv_grads(src, params["e%da" % l], g)
     return grads

@@ -26,6 +26,11 @@ DAS_IQ_C16BF = 2
 EXPORTED = ("das_plan_create", "das_execute", "das_plan_destroy", "das_tx_plane_wave", "das_plan_query",
             "das_tile_order", "das_status_string", "das_last_error", "das_version")
 
+# Every symbol include/das_learn.h declares.
+LEARN_EXPORTED = ("das_conv3d", "das_conv3d_wgrad", "das_conv3d_wgrad_work", "das_transpose_weights",
+                  "das_avgpool2", "das_avgpool2_bwd", "das_upsample2", "das_upsample2_bwd", "das_add_mask",
+                  "das_mse_residual", "das_adam", "das_f32_to_bf16", "das_learn_last_error")
+
 
 class DasParams(ctypes.Structure):
     _fields_ = [("n_tx", ctypes.c_int32), ("n_elem", ctypes.c_int32), ("n_samples", ctypes.c_int32),
@@ -72,8 +77,34 @@ def load():
     lib.das_last_error.restype = ctypes.c_char_p
     lib.das_version.argtypes = []
     lib.das_version.restype = ctypes.c_int
+    _declare_learn(lib)
     _lib = lib
     return lib
+
+
+def _declare_learn(lib):
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
+    sig = {
+        "das_conv3d": [vp, i32, i32, vp, vp, vp, i32, i32, i32, vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, vp],
+        "das_conv3d_wgrad": [vp, i32, i32, vp, i32, i32, vp, vp, vp, i64, i32, i32, i32, i32, i32, i32, vp],
+        "das_conv3d_wgrad_work": [i32, i32, i32, i32, i32, i32],
+        "das_transpose_weights": [vp, vp, i32, i32, vp],
+        "das_avgpool2": [vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp],
+        "das_avgpool2_bwd": [vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, i32, vp],
+        "das_upsample2": [vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp],
+        "das_upsample2_bwd": [vp, i32, i32, vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp],
+        "das_add_mask": [vp, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, i32, i64, i32, vp],
+        "das_mse_residual": [vp, i32, vp, vp, i64, vp, i32, vp, vp, vp],
+        "das_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
+        "das_f32_to_bf16": [vp, vp, i64, vp],
+        "das_learn_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.das_conv3d_wgrad_work.restype = i64
+    lib.das_learn_last_error.restype = ctypes.c_char_p
 
 
 class DasError(RuntimeError):
@@ -92,11 +123,11 @@ class DasValueError(ValueError):
         self.status = status
 
 
-def check(status):
+def check(status, learn=False):
     """Raise on a negative libdas status (ValueError for argument errors)."""
     if status == DAS_OK:
         return
-    msg = load().das_last_error().decode()
+    msg = (load().das_learn_last_error() if learn else load().das_last_error()).decode()
     if status in (DAS_EINVAL, DAS_ESHAPE, DAS_EDTYPE, DAS_EALIGN):
         raise DasValueError(status, msg)
     raise DasError(status, msg)

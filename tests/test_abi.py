@@ -154,3 +154,42 @@ def test_tiling_partial_lattice_and_point_cloud():
     assert s2v.size == 0
     with pytest.raises(ValueError):
         das.tile_order(np.array([[0.0, 0.0, np.nan]], np.float32))
+
+
+# ----------------------------------------------------------------- learned compounding ABI
+LEARN_HEADER = os.path.join(ROOT, "include", "das_learn.h")
+
+
+def test_learn_header_declares_what_the_binding_expects():
+    text = re.sub(r"/\*.*?\*/", "", open(LEARN_HEADER).read(), flags=re.S)
+    assert sorted(set(re.findall(r"\b(das_\w+)\s*\(", text))) == sorted(_lib.LEARN_EXPORTED)
+    lib = _lib.load()
+    for name in _lib.LEARN_EXPORTED:
+        assert hasattr(lib, name), name
+
+
+def test_learn_entry_points_reject_bad_args():
+    lib = _lib.load()
+    F = FAKE
+    # conv3d: Cin not a multiple of 8, Cout above 128, null input, misaligned weights, slice outside buffer
+    assert lib.das_conv3d(F, 8, 0, F, None, F, 16, 0, 0, None, 0, 0, 4, 4, 4, 4, 16, 0, 0, None) == _lib.DAS_ESHAPE
+    assert lib.das_conv3d(F, 8, 0, F, None, F, 144, 0, 0, None, 0, 0, 4, 4, 4, 8, 144, 0, 0, None) == _lib.DAS_ESHAPE
+    assert lib.das_conv3d(None, 8, 0, F, None, F, 16, 0, 0, None, 0, 0, 4, 4, 4, 8, 16, 0, 0, None) == _lib.DAS_EINVAL
+    assert lib.das_conv3d(F, 8, 0, ctypes.c_void_p(0x1008), None, F, 16, 0, 0, None, 0, 0, 4, 4, 4, 8, 16, 0, 0,
+                          None) == _lib.DAS_EALIGN
+    assert lib.das_conv3d(F, 8, 8, F, None, F, 16, 0, 0, None, 0, 0, 4, 4, 4, 8, 16, 0, 0, None) == _lib.DAS_ESHAPE
+    assert lib.das_conv3d(F, 8, 0, F, None, F, 16, 0, 0, None, 0, 0, 0, 4, 4, 8, 16, 0, 0, None) == _lib.DAS_ESHAPE
+    assert len(lib.das_learn_last_error()) > 0
+    # wgrad: chunk not a multiple of 32, work space too small
+    assert lib.das_conv3d_wgrad(F, 8, 0, F, 16, 0, F, F, F, 10**9, 4, 4, 4, 8, 16, 48, None) == _lib.DAS_ESHAPE
+    need = lib.das_conv3d_wgrad_work(4, 4, 4, 8, 16, 32)
+    assert need == 2 * (16 * 27 * 8 + 16)
+    assert lib.das_conv3d_wgrad(F, 8, 0, F, 16, 0, F, F, F, need - 1, 4, 4, 4, 8, 16, 32, None) == _lib.DAS_ESHAPE
+    # Adam counts steps from 1
+    assert lib.das_adam(F, F, F, F, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == _lib.DAS_EINVAL
+    assert lib.das_mse_residual(F, 1, F, F, 10, None, 0, None, F, None) == _lib.DAS_ESHAPE
+    # pooling / upsampling: odd sizes and slices outside their buffers
+    assert lib.das_avgpool2_bwd(F, 16, 0, F, 16, 0, 5, 4, 4, 16, 0, None) == _lib.DAS_ESHAPE
+    assert lib.das_upsample2(F, 16, 0, F, 16, 0, 4, 3, 4, 16, None) == _lib.DAS_ESHAPE
+    assert lib.das_avgpool2(F, 16, 8, F, 16, 0, 2, 2, 2, 16, None) == _lib.DAS_ESHAPE
+    assert lib.das_add_mask(F, 16, 0, F, 8, 0, None, 0, 0, F, 16, 0, 10, 16, None) == _lib.DAS_ESHAPE
