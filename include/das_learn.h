@@ -97,6 +97,30 @@ int das_adam(float *w, float *m, float *v, const float *g, void *w_bf16, int64_t
 /* y = bfloat16(x), round to nearest even. */
 int das_f32_to_bf16(const float *x, void *y, int64_t n, void *stream);
 
+/* Inputs of the network from n_in beamformed volumes y (complex64 [n_in][V],
+ * one plane wave each): rms = sqrt(mean_v |sum_a y_a[v]|^2) (the RMS of the
+ * few-angle compound); x[v][2a], x[v][2a+1] = bfloat16(Re, Im of y_a[v] / rms)
+ * and x[v][c] = 0 for 2 n_in <= c < cin (x is bfloat16 [V][cin]); base (float32
+ * [V][2], may be NULL) = gain * sum_a y_a[v] / rms.  scale (device, 2 floats)
+ * receives {rms, 1 / rms} (1 / rms = 0 when rms = 0).  work holds
+ * das_compound_work(V) floats.  Sum of squares in float32 per 256 voxels,
+ * then float64. */
+int das_compound_features(const void *y, int n_in, int64_t V, float gain, void *x, int cin, float *base, float *work,
+                          float *scale, void *stream);
+
+/* Floats of work space das_compound_features needs (host call). */
+int64_t das_compound_work(int64_t V);
+
+/* out = y * (restore ? rms : 1 / rms) for complex64 [V] volumes and the scale of
+ * das_compound_features: normalises a target, or returns a prediction to the
+ * beamformer's units.  out may equal y. */
+int das_compound_rescale(const void *y, int64_t V, const float *scale, int restore, void *out, void *stream);
+
+/* out[v] = (base[v] + net[v][0:2]) * rms (complex64 [V]): the learned compound
+ * in the beamformer's units; scale from das_compound_features. */
+int das_compound_output(const float *net, int net_stride, const float *base, int64_t V, const float *scale, void *out,
+                        void *stream);
+
 /* Thread-local message of the last failing call of this header ("" if none). */
 const char *das_learn_last_error(void);
 

@@ -29,7 +29,8 @@ EXPORTED = ("das_plan_create", "das_execute", "das_plan_destroy", "das_tx_plane_
 # Every symbol include/das_learn.h declares.
 LEARN_EXPORTED = ("das_conv3d", "das_conv3d_wgrad", "das_conv3d_wgrad_work", "das_transpose_weights",
                   "das_avgpool2", "das_avgpool2_bwd", "das_upsample2", "das_upsample2_bwd", "das_add_mask",
-                  "das_mse_residual", "das_adam", "das_f32_to_bf16", "das_learn_last_error")
+                  "das_mse_residual", "das_adam", "das_f32_to_bf16", "das_compound_features", "das_compound_work",
+                  "das_compound_rescale", "das_compound_output", "das_learn_last_error")
 
 
 class DasParams(ctypes.Structure):
@@ -97,6 +98,10 @@ def _declare_learn(lib):
         "das_mse_residual": [vp, i32, vp, vp, i64, vp, i32, vp, vp, vp],
         "das_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
         "das_f32_to_bf16": [vp, vp, i64, vp],
+        "das_compound_features": [vp, i32, i64, f32, vp, i32, vp, vp, vp, vp],
+        "das_compound_work": [i64],
+        "das_compound_rescale": [vp, i64, vp, i32, vp, vp],
+        "das_compound_output": [vp, i32, vp, i64, vp, vp, vp],
         "das_learn_last_error": [],
     }
     for name, args in sig.items():
@@ -104,6 +109,7 @@ def _declare_learn(lib):
         fn.argtypes = args
         fn.restype = ctypes.c_int
     lib.das_conv3d_wgrad_work.restype = i64
+    lib.das_compound_work.restype = i64
     lib.das_learn_last_error.restype = ctypes.c_char_p
 
 

@@ -310,6 +310,92 @@ __global__ void f32_to_bf16_kernel(const float* __restrict__ x, uint16_t* __rest
     if (i < n) y[i] = f2bf(x[i]);
 }
 
+
+// ---- compounding features
+// part[b] = sum over the block's voxels of |sum_a y_a[v]|^2   (y complex64 [A][V])
+__global__ __launch_bounds__(256) void sumsq_kernel(const float2* __restrict__ y, int A, int64_t V,
+                                                    float* __restrict__ part) {
+    __shared__ float red[256];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float l = 0.0f;
+    if (v < V) {
+        float re = 0.0f, im = 0.0f;
+        for (int a = 0; a < A; ++a) {
+            const float2 z = y[(int64_t)a * V + v];
+            re += z.x;
+            im += z.y;
+        }
+        l = re * re + im * im;
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// scale[0] = sqrt(sum(part) / V) (the RMS), scale[1] = 1 / scale[0] (0 for an all-zero input); one block.
+__global__ __launch_bounds__(256) void rms_kernel(const float* __restrict__ part, int nparts, int64_t V,
+                                                  float* __restrict__ scale) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float rms = (float)sqrt(red[0] / (double)V);
+        scale[0] = rms;
+        scale[1] = rms > 0.0f ? 1.0f / rms : 0.0f;
+    }
+}
+
+// x[v][2a + {0,1}] = bf16(y_a[v] / rms), x[v][c >= 2A] = 0; base[v] = gain * sum_a y_a[v] / rms
+__global__ __launch_bounds__(256) void features_kernel(const float2* __restrict__ y, int A, int64_t V, float gain,
+                                                       const float* __restrict__ scale, uint16_t* __restrict__ x,
+                                                       int cin, float* __restrict__ base) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= V) return;
+    const float inv = scale[1];
+    float re = 0.0f, im = 0.0f;
+    for (int a = 0; a < A; ++a) {
+        const float2 z = y[(int64_t)a * V + v];
+        re += z.x;
+        im += z.y;
+        x[v * cin + 2 * a] = f2bf(z.x * inv);
+        x[v * cin + 2 * a + 1] = f2bf(z.y * inv);
+    }
+    for (int c = 2 * A; c < cin; ++c) x[v * cin + c] = 0;
+    if (base) {
+        base[2 * v] = gain * re * inv;
+        base[2 * v + 1] = gain * im * inv;
+    }
+}
+
+// out[v] = y[v] * scale[k]: k = 1 normalises a complex64 volume, k = 0 restores physical units
+__global__ void rescale_kernel(const float2* __restrict__ y, int64_t V, const float* __restrict__ scale, int k,
+                               float2* __restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float s = scale[k];
+    const float2 z = y[v];
+    out[v] = make_float2(z.x * s, z.y * s);
+}
+
+// out[v] = (base[v] + net[v][0:2]) * rms: the network's estimate in the beamformer's units (complex64)
+__global__ void compound_output_kernel(const float* __restrict__ net, int net_stride, const float* __restrict__ base,
+                                       int64_t V, const float* __restrict__ scale, float2* __restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float s = scale[0];
+    out[v] = make_float2((base[2 * v] + net[v * net_stride]) * s, (base[2 * v + 1] + net[v * net_stride + 1]) * s);
+}
+
 }  // namespace learn
 
 // ------------------------------------------------------------------ C ABI
@@ -490,6 +576,44 @@ int das_f32_to_bf16(const float* x, void* y, int64_t n, void* stream) {
     hipLaunchKernelGGL(learn::f32_to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), x, reinterpret_cast<uint16_t*>(y), n);
     return launch_status("cast launch failed");
+}
+
+
+int das_compound_features(const void* y, int n_in, int64_t V, float gain, void* x, int cin, float* base, float* work,
+                          float* scale, void* stream) {
+    if (!y || !x || !work || !scale) return lfail(DAS_EINVAL, "compound_features: null pointer");
+    if (n_in < 1 || V < 1 || cin < 2 * n_in) return lfail(DAS_ESHAPE, "compound_features: need V >= 1, cin >= 2 n_in");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const float2* yy = reinterpret_cast<const float2*>(y);
+    const unsigned nb = blocks_for(V, 256);
+    hipLaunchKernelGGL(learn::sumsq_kernel, dim3(nb), dim3(256), 0, s, yy, n_in, V, work);
+    hipLaunchKernelGGL(learn::rms_kernel, dim3(1), dim3(256), 0, s, work, (int)nb, V, scale);
+    hipLaunchKernelGGL(learn::features_kernel, dim3(nb), dim3(256), 0, s, yy, n_in, V, gain, scale,
+                       reinterpret_cast<uint16_t*>(x), cin, base);
+    return launch_status("compound_features launch failed");
+}
+
+int64_t das_compound_work(int64_t V) { return V < 1 ? 0 : (V + 255) / 256; }
+
+int das_compound_rescale(const void* y, int64_t V, const float* scale, int restore, void* out, void* stream) {
+    if (!y || !scale || !out) return lfail(DAS_EINVAL, "compound_rescale: null pointer");
+    if (V < 0) return lfail(DAS_ESHAPE, "compound_rescale: V < 0");
+    if (V == 0) return DAS_OK;
+    hipLaunchKernelGGL(learn::rescale_kernel, dim3(blocks_for(V, 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const float2*>(y), V, scale,
+                       restore ? 0 : 1, reinterpret_cast<float2*>(out));
+    return launch_status("compound_rescale launch failed");
+}
+
+int das_compound_output(const float* net, int net_stride, const float* base, int64_t V, const float* scale, void* out,
+                        void* stream) {
+    if (!net || !base || !scale || !out) return lfail(DAS_EINVAL, "compound_output: null pointer");
+    if (V < 0 || net_stride < 2) return lfail(DAS_ESHAPE, "compound_output: V < 0 or net_stride < 2");
+    if (V == 0) return DAS_OK;
+    hipLaunchKernelGGL(learn::compound_output_kernel, dim3(blocks_for(V, 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), net, net_stride, base, V, scale,
+                       reinterpret_cast<float2*>(out));
+    return launch_status("compound_output launch failed");
 }
 
 }  // extern "C"

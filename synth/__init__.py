@@ -14,5 +14,5 @@ loss, attenuation or element directivity.
 """
 
 from .geometry import linear_array, matrix_array, grid_2d, grid_3d  # noqa: F401
-from .echo import echo_iq, echo_iq_numpy, plane_wave_normals  # noqa: F401
-from .configs import make_config, CONFIGS  # noqa: F401
+from .echo import echo_iq, echo_iq_numpy, echo_iq_gpu, plane_wave_normals  # noqa: F401
+from .configs import make_config, volume_phantom, CONFIGS  # noqa: F401

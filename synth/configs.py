@@ -70,7 +70,7 @@ def _disk_phantom(rng, n_frames, grid_x, grid_z):
     return scat, amp
 
 
-def _volume_phantom(rng, n_frames, lo, hi, n_speckle=20000, n_points=50, point_amp=10.0):
+def volume_phantom(rng, n_frames, lo, hi, n_speckle=20000, n_points=50, point_amp=10.0):
     """Per-frame independent speckle in a box plus fixed bright points."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
@@ -139,7 +139,7 @@ def make_config(name, seed=None, *, with_iq=True, n_frames=None, angles_deg=None
             ang = np.asarray(angles_deg, float).reshape(-1, 2) * DEG
         lo = (xs[0], xs[0], zs[0])
         hi = (xs[-1], xs[-1], zs[-1])
-        scat, amp = _volume_phantom(rng, p["n_frames"], lo, hi)
+        scat, amp = volume_phantom(rng, p["n_frames"], lo, hi)
         noise_std = 0.0
     out.update(elem=elem, vox=vox, angles=ang, params=p, grid_shape=grid_shape, scat=scat, amp=amp)
     if with_iq:
