@@ -32,6 +32,9 @@ LEARN_EXPORTED = ("das_conv3d", "das_conv3d_wgrad", "das_conv3d_wgrad_work", "da
                   "das_mse_residual", "das_adam", "das_f32_to_bf16", "das_compound_features", "das_compound_work",
                   "das_compound_rescale", "das_compound_output", "das_learn_last_error")
 
+# Every symbol include/das_post.h declares.
+POST_EXPORTED = ("das_bmode", "das_bmode_work", "das_power_doppler", "das_power_doppler_work", "das_post_last_error")
+
 
 class DasParams(ctypes.Structure):
     _fields_ = [("n_tx", ctypes.c_int32), ("n_elem", ctypes.c_int32), ("n_samples", ctypes.c_int32),
@@ -108,6 +111,16 @@ def _declare_learn(lib):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    post = {"das_bmode": [vp, i64, i32, f32, vp, vp, i64, vp], "das_bmode_work": [i64, i32],
+            "das_power_doppler": [vp, i64, i32, i32, vp, vp, i64, vp], "das_power_doppler_work": [i64, i32],
+            "das_post_last_error": []}
+    for name, args in post.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.das_bmode_work.restype = i64
+    lib.das_power_doppler_work.restype = i64
+    lib.das_post_last_error.restype = ctypes.c_char_p
     lib.das_conv3d_wgrad_work.restype = i64
     lib.das_compound_work.restype = i64
     lib.das_learn_last_error.restype = ctypes.c_char_p
@@ -129,11 +142,12 @@ class DasValueError(ValueError):
         self.status = status
 
 
-def check(status, learn=False):
+def check(status, learn=False, post=False):
     """Raise on a negative libdas status (ValueError for argument errors)."""
     if status == DAS_OK:
         return
-    msg = (load().das_learn_last_error() if learn else load().das_last_error()).decode()
+    lib = load()
+    msg = (lib.das_post_last_error() if post else lib.das_learn_last_error() if learn else lib.das_last_error()).decode()
     if status in (DAS_EINVAL, DAS_ESHAPE, DAS_EDTYPE, DAS_EALIGN):
         raise DasValueError(status, msg)
     raise DasError(status, msg)

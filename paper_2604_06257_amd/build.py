@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdas.so")
-SOURCES = ["das_api.cpp", "das_kernels.hip", "learn_kernels.hip"]
+SOURCES = ["das_api.cpp", "das_kernels.hip", "learn_kernels.hip", "post_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -193,3 +193,30 @@ def test_learn_entry_points_reject_bad_args():
     assert lib.das_upsample2(F, 16, 0, F, 16, 0, 4, 3, 4, 16, None) == _lib.DAS_ESHAPE
     assert lib.das_avgpool2(F, 16, 8, F, 16, 0, 2, 2, 2, 16, None) == _lib.DAS_ESHAPE
     assert lib.das_add_mask(F, 16, 0, F, 8, 0, None, 0, 0, F, 16, 0, 10, 16, None) == _lib.DAS_ESHAPE
+
+
+# ----------------------------------------------------------------- post-processing ABI
+def test_post_header_declares_what_the_binding_expects():
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "das_post.h")).read(), flags=re.S)
+    assert sorted(set(re.findall(r"\b(das_\w+)\s*\(", text))) == sorted(_lib.POST_EXPORTED)
+    lib = _lib.load()
+    for name in _lib.POST_EXPORTED:
+        assert hasattr(lib, name), name
+
+
+def test_post_entry_points_reject_bad_args():
+    lib = _lib.load()
+    F = FAKE
+    need = lib.das_bmode_work(1000, 4)
+    assert need == 4 * 4 + 4
+    assert lib.das_bmode(F, 1000, 4, 60.0, F, F, need - 1, None) == _lib.DAS_ESHAPE
+    assert lib.das_bmode(F, 1000, 4, 0.0, F, F, need, None) == _lib.DAS_EINVAL
+    assert lib.das_bmode(F, 0, 4, 60.0, F, F, need, None) == _lib.DAS_ESHAPE
+    assert lib.das_bmode(None, 1000, 4, 60.0, F, F, need, None) == _lib.DAS_EINVAL
+    pneed = lib.das_power_doppler_work(1000, 32)
+    assert pneed > 2 * 32 * 32
+    assert lib.das_power_doppler(F, 1000, 33, 1, F, F, 10 ** 9, None) == _lib.DAS_ESHAPE
+    assert lib.das_power_doppler(F, 1000, 32, 33, F, F, pneed, None) == _lib.DAS_EINVAL
+    assert lib.das_power_doppler(F, 1000, 32, -1, F, F, pneed, None) == _lib.DAS_EINVAL
+    assert lib.das_power_doppler(F, 1000, 32, 1, F, F, pneed - 1, None) == _lib.DAS_ESHAPE
+    assert len(lib.das_post_last_error()) > 0
