@@ -34,129 +34,202 @@ struct Vol {
 
 constexpr int kMaxNT = 8;  // up to 128 output channels per launch
 
-// out[v][n] = act(sum_{tap,c} in[v + s*off(tap)][c] * wk[n][tap*Cin + c] + bias[n]) * mask
-template <bool OUT_F32>
+// Convolution on a brick of 8 (W) x 8 (H) x MT (D) output voxels per workgroup of 4 waves.  Wave w owns the
+// 4 x 4 (W x H) patch w of every depth slice (one 16-voxel MFMA row tile per slice) and NT x 16 output
+// channels.  The input brick with its one-voxel halo, 10 x 10 x (MT + 2) voxels, is staged in LDS one
+// channel chunk (CC channels) at a time, so each input value is read from global memory once per chunk
+// instead of once per tap; the operand-A fragments of all 27 taps are then 16-byte LDS reads.  Weights
+// (operand B) come from global memory (shared by all waves through the caches), one K step ahead.
+constexpr int kHaloW = 10, kHaloH = 10;
+
+template <int MT, int NT, int CC>
 __global__ __launch_bounds__(256) void conv3d_kernel(const uint16_t* __restrict__ in, int in_stride, int in_coff,
                                                      const uint16_t* __restrict__ wk, const float* __restrict__ bias,
-                                                     void* __restrict__ out, int out_stride, int out_coff,
+                                                     void* __restrict__ out, int out_stride, int out_coff, int out_f32,
                                                      const uint16_t* __restrict__ mask, int mask_stride, int mask_coff,
-                                                     Vol vol, int Cin, int Cout, int flip, int relu) {
+                                                     Vol vol, int Cin, int flip, int relu) {
+    constexpr int HD = MT + 2;
+    constexpr int NHALO = kHaloW * kHaloH * HD;
+    constexpr int VP = CC + 8;                 // LDS elements per halo voxel (padding spreads the banks)
+    constexpr int KSTEPS = (27 * CC + 31) / 32;  // K steps per channel chunk
+    __shared__ __attribute__((aligned(16))) uint16_t halo[NHALO * VP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t V = (int64_t)vol.D * vol.H * vol.W;
-    const int64_t v0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (v0 >= V) return;  // whole wave past the end (no barriers in this kernel)
+    const int nbw = (vol.W + 7) / 8, nbh = (vol.H + 7) / 8;
+    const int bx = blockIdx.x % nbw, by = (blockIdx.x / nbw) % nbh, bz = blockIdx.x / (nbw * nbh);
+    const int w0 = 8 * bx, h0 = 8 * by, d0 = MT * bz;
     const int K = 27 * Cin;
-    const int NT = Cout / 16;
-    // operand-A voxel of this lane
-    const int64_t va = v0 + (lane & 15);
-    const bool va_ok = va < V;
-    const int aw = (int)(va % vol.W), ah = (int)((va / vol.W) % vol.H), ad = (int)(va / ((int64_t)vol.W * vol.H));
     const int s = flip ? -1 : 1;
-    f32x4 acc[kMaxNT];
+    // this lane's operand-A voxel within its wave's patch (row lane & 15 of the MFMA tile)
+    const int pw = 4 * (wave & 1), ph = 4 * (wave >> 1);
+    const int rw = pw + (lane & 3), rh = ph + ((lane >> 2) & 3);
+    f32x4 acc[MT][NT];
 #pragma unroll
-    for (int t = 0; t < kMaxNT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kc = 0; kc < K; kc += 32) {
-        const int k = kc + 8 * (lane >> 4);
-        bf16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (k < K && va_ok) {
-            const int tap = k / Cin, c = k - tap * Cin;
-            const int zd = ad + s * (tap / 9 - 1), zh = ah + s * ((tap / 3) % 3 - 1), zw = aw + s * (tap % 3 - 1);
-            if (zd >= 0 && zd < vol.D && zh >= 0 && zh < vol.H && zw >= 0 && zw < vol.W) {
-                const int64_t nb = ((int64_t)zd * vol.H + zh) * vol.W + zw;
-                a = *reinterpret_cast<const bf16x8*>(in + nb * in_stride + in_coff + c);
-            }
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int g = lane >> 4;  // 8-element group of the K step
+    for (int cc0 = 0; cc0 < Cin; cc0 += CC) {
+        __syncthreads();
+        // stage the halo brick for channels [cc0, cc0 + CC): 16 bytes per item
+        for (int it = threadIdx.x; it < NHALO * (CC / 8); it += 256) {
+            const int hv = it / (CC / 8), c8 = it - hv * (CC / 8);
+            const int hx = hv % kHaloW, hy = (hv / kHaloW) % kHaloH, hz = hv / (kHaloW * kHaloH);
+            const int zw = w0 - 1 + hx, zh = h0 - 1 + hy, zd = d0 - 1 + hz;
+            bf16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+            if ((unsigned)zw < (unsigned)vol.W && (unsigned)zh < (unsigned)vol.H && (unsigned)zd < (unsigned)vol.D)
+                val = *reinterpret_cast<const bf16x8*>(
+                    in + (((int64_t)zd * vol.H + zh) * vol.W + zw) * in_stride + in_coff + cc0 + 8 * c8);
+            *reinterpret_cast<bf16x8*>(&halo[hv * VP + 8 * c8]) = val;
         }
+        __syncthreads();
+        bf16x8 b[NT], bn[NT];
+        auto load_b = [&](int ks, bf16x8(&dst)[NT]) {
+            const int kl = 32 * ks + 8 * g, tap = kl / CC, c = kl - tap * CC;
 #pragma unroll
-        for (int t = 0; t < kMaxNT; ++t) {
-            if (t < NT) {
-                bf16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (k < K) b = *reinterpret_cast<const bf16x8*>(wk + (int64_t)(t * 16 + (lane & 15)) * K + k);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) {
+                dst[t] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (tap < 27)
+                    dst[t] = *reinterpret_cast<const bf16x8*>(wk + (int64_t)(t * 16 + (lane & 15)) * K + tap * Cin +
+                                                             cc0 + c);
             }
+        };
+        load_b(0, b);
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            if (ks + 1 < KSTEPS) load_b(ks + 1, bn);
+            const int kl = 32 * ks + 8 * g, tap = kl / CC, c = kl - tap * CC;
+            const int dz = s * (tap / 9 - 1), dyy = s * ((tap / 3) % 3 - 1), dx = s * (tap % 3 - 1);
+            bf16x8 a[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                a[m] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (tap < 27) {
+                    const int hv = ((m + 1 + dz) * kHaloH + (rh + 1 + dyy)) * kHaloW + (rw + 1 + dx);
+                    a[m] = *reinterpret_cast<const bf16x8*>(&halo[hv * VP + c]);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[t], acc[m][t], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[t] = bn[t];
         }
     }
+    // result rows 4 (lane / 16) + r of the tile: voxel (pw + r, ph + lane / 16) of the patch
 #pragma unroll
-    for (int t = 0; t < kMaxNT; ++t) {
-        if (t >= NT) break;
+    for (int t = 0; t < NT; ++t) {
         const int n = t * 16 + (lane & 15);
-        const float bn = bias ? bias[n] : 0.0f;
+        const float bn_ = bias ? bias[n] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t v = v0 + 4 * (lane >> 4) + r;
-            if (v >= V) continue;
-            float y = acc[t][r] + bn;
-            if (relu) y = fmaxf(y, 0.0f);
-            if (mask && !(bf2f(mask[v * mask_stride + mask_coff + n]) > 0.0f)) y = 0.0f;
-            if (OUT_F32) reinterpret_cast<float*>(out)[v * out_stride + out_coff + n] = y;
-            else reinterpret_cast<uint16_t*>(out)[v * out_stride + out_coff + n] = f2bf(y);
+        for (int m = 0; m < MT; ++m) {
+            const int zd = d0 + m, zh = h0 + ph + (lane >> 4);
+            if (zd >= vol.D || zh >= vol.H) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int zw = w0 + pw + r;
+                if (zw >= vol.W) continue;
+                const int64_t v = ((int64_t)zd * vol.H + zh) * vol.W + zw;
+                float y = acc[m][t][r] + bn_;
+                if (relu) y = fmaxf(y, 0.0f);
+                if (mask && !(bf2f(mask[v * mask_stride + mask_coff + n]) > 0.0f)) y = 0.0f;
+                if (out_f32) reinterpret_cast<float*>(out)[v * out_stride + out_coff + n] = y;
+                else reinterpret_cast<uint16_t*>(out)[v * out_stride + out_coff + n] = f2bf(y);
+            }
         }
     }
 }
 
 // Weight gradient, split over voxel chunks:
 //   part[b][n][k] = sum_{v in chunk b} dy[v][n] * in[v + off(tap k)][c k],  part_db[b][n] = sum_v dy[v][n]
-// MFMA with M = output channel n, N = k, reduction over voxels (32 per step).
-__global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__ in, int in_stride, int in_coff,
-                                                    const uint16_t* __restrict__ dy, int dy_stride, int dy_coff,
-                                                    float* __restrict__ part, float* __restrict__ part_db, Vol vol,
-                                                    int Cin, int Cout, int chunk) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// One wave per workgroup owns (chunk, tap, NB x 16 output channels, CB x 16 input channels).  The reduction
+// runs over voxels, which are not contiguous for a fixed channel in the channels-last layout, so every
+// 32-voxel step stages dy and the shifted input transposed into LDS ([channel][voxel]); both MFMA operands
+// are then one 16-byte LDS read per lane.
+constexpr int kWgPitch = 40;  // LDS row: 32 voxels + 8 pad (80 B: 16-byte aligned, rows spread over banks)
+
+template <int NB, int CB>
+__global__ __launch_bounds__(64) void wgrad_kernel(const uint16_t* __restrict__ in, int in_stride, int in_coff,
+                                                   const uint16_t* __restrict__ dy, int dy_stride, int dy_coff,
+                                                   float* __restrict__ part, float* __restrict__ part_db, Vol vol,
+                                                   int Cin, int Cout, int chunk, int n_cgroups) {
+    __shared__ __attribute__((aligned(16))) uint16_t dyT[NB * 16 * kWgPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t xT[CB * 16 * kWgPitch];
+    const int lane = threadIdx.x;
     const int64_t V = (int64_t)vol.D * vol.H * vol.W;
     const int K = 27 * Cin;
-    const int NT = Cout / 16, KT = (K + 15) / 16;
-    const int64_t vbeg = (int64_t)blockIdx.x * chunk;
+    const int b = blockIdx.x, tap = blockIdx.y;
+    const int ng = blockIdx.z / n_cgroups, cg = blockIdx.z - ng * n_cgroups;
+    const int n0 = ng * NB * 16, c0 = cg * CB * 16;
+    const int64_t vbeg = (int64_t)b * chunk;
     const int64_t vend = (vbeg + chunk < V) ? vbeg + chunk : V;
-    float* pb = part + (int64_t)blockIdx.x * Cout * K;
-    // output tiles (n tile, k tile) distributed over the 4 waves
-    for (int tile = wave; tile < NT * KT; tile += 4) {
-        const int nt = tile / KT, kt = tile - nt * KT;
-        const int n = nt * 16 + (lane & 15);       // A row of this lane
-        const int kb = kt * 16 + (lane & 15);      // B column of this lane
-        const bool kb_ok = kb < K;
-        const int tap = kb_ok ? kb / Cin : 0, c = kb_ok ? kb - tap * Cin : 0;
-        const int od = tap / 9 - 1, oh = (tap / 3) % 3 - 1, ow = tap % 3 - 1;
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int64_t vc = vbeg; vc < vend; vc += 32) {
-            bf16x8 a, b;
-            // coordinates of this lane's first voxel, then stepped along w
-            const int64_t vs = vc + 8 * (lane >> 4);
-            int w = (int)(vs % vol.W), h = (int)((vs / vol.W) % vol.H), d = (int)(vs / ((int64_t)vol.W * vol.H));
+    const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    const int64_t off = ((int64_t)dz * vol.H + dyy) * vol.W + dx;
+    const bool do_db = (tap == 0 && cg == 0);
+    f32x4 acc[NB][CB];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t v = vs + j;
-                short av = 0, bv = 0;
-                if (v < vend) {
-                    av = (short)dy[v * dy_stride + dy_coff + n];
-                    if (kb_ok) {
-                        const int zd = d + od, zh = h + oh, zw = w + ow;
-                        if (zd >= 0 && zd < vol.D && zh >= 0 && zh < vol.H && zw >= 0 && zw < vol.W)
-                            bv = (short)in[(((int64_t)zd * vol.H + zh) * vol.W + zw) * in_stride + in_coff + c];
-                    }
-                }
-                a[j] = av;
-                b[j] = bv;
-                if (++w == vol.W) {
-                    w = 0;
-                    if (++h == vol.H) {
-                        h = 0;
-                        ++d;
-                    }
-                }
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float dbs = 0.0f;
+    // staging map: lane -> (voxel = lane % 32, 8-channel group = lane / 32 + 2 r)
+    const int sv = lane & 31, sg = lane >> 5;
+    for (int64_t vc = vbeg; vc < vend; vc += 32) {
+        const int64_t v = vc + sv;
+        const bool vin = v < vend;
+        int w = 0, h = 0, d = 0;
+        if (vin) {  // V < 2^31: 32-bit index arithmetic
+            const uint32_t vu = (uint32_t)v, q = vu / (uint32_t)vol.W;
+            w = (int)(vu - q * (uint32_t)vol.W);
+            h = (int)(q % (uint32_t)vol.H);
+            d = (int)(q / (uint32_t)vol.H);
+        }
+        const bool nbr = vin && (unsigned)(d + dz) < (unsigned)vol.D && (unsigned)(h + dyy) < (unsigned)vol.H &&
+                         (unsigned)(w + dx) < (unsigned)vol.W;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int g = sg + 2 * r;  // 8-channel group within the NB x 16 output channels
+            bf16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (vin) val = *reinterpret_cast<const bf16x8*>(dy + v * dy_stride + dy_coff + n0 + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dyT[(8 * g + j) * kWgPitch + sv] = (uint16_t)val[j];
+        }
+#pragma unroll
+        for (int r = 0; r < CB; ++r) {
+            const int g = sg + 2 * r;
+            const int c = c0 + 8 * g;
+            bf16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (nbr && c < Cin) val = *reinterpret_cast<const bf16x8*>(in + (v + off) * in_stride + in_coff + c);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xT[(8 * g + j) * kWgPitch + sv] = (uint16_t)val[j];
+        }
+        __syncthreads();
+        bf16x8 A[NB], B[CB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            A[i] = *reinterpret_cast<const bf16x8*>(&dyT[(i * 16 + (lane & 15)) * kWgPitch + 8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+            B[j] = *reinterpret_cast<const bf16x8*>(&xT[(j * 16 + (lane & 15)) * kWgPitch + 8 * (lane >> 4)]);
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+        if (do_db && lane < NB * 16)
+            for (int u = 0; u < 32; ++u) dbs += bf2f(dyT[lane * kWgPitch + u]);
+    }
+    float* pb = part + (int64_t)b * Cout * K;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = n0 + i * 16 + 4 * (lane >> 4) + r, c = c0 + j * 16 + (lane & 15);
+                if (c < Cin) pb[(int64_t)n * K + tap * Cin + c] = acc[i][j][r];
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int nn = nt * 16 + 4 * (lane >> 4) + r, kk = kt * 16 + (lane & 15);
-            if (kk < K) pb[(int64_t)nn * K + kk] = acc[r];
-        }
-    }
-    // bias partial: one thread per output channel, fixed voxel order
-    for (int n = threadIdx.x; n < Cout; n += 256) {
-        float sacc = 0.0f;
-        for (int64_t v = vbeg; v < vend; ++v) sacc += bf2f(dy[v * dy_stride + dy_coff + n]);
-        part_db[(int64_t)blockIdx.x * Cout + n] = sacc;
-    }
+    if (do_db && lane < NB * 16) part_db[(int64_t)b * Cout + n0 + lane] = dbs;
 }
 
 // dw[i] = sum_b part[b][i] in chunk order (deterministic), i over Cout * K; same for db.
@@ -414,6 +487,76 @@ int launch_status(const char* what) {
     if (e != hipSuccess) return lfail(DAS_EHIP, what);
     return DAS_OK;
 }
+
+// Depth slices per workgroup: 4 when the output has at most 32 channels, 2 up to 64, else 1; channel chunk:
+// the largest of 32, 16, 8 that divides Cin.
+template <int NT, int CC>
+void launch_conv_t(int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride, int in_coff,
+                   const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff, const uint16_t* mk,
+                   int mask_stride, int mask_coff, int cin, int flip, int relu) {
+    constexpr int MT = NT <= 2 ? 4 : (NT <= 4 ? 2 : 1);
+    const unsigned nb = (unsigned)(((vol.W + 7) / 8) * ((vol.H + 7) / 8) * ((vol.D + MT - 1) / MT));
+    hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC>), dim3(nb), dim3(256), 0, s, x, in_stride, in_coff, w, bias,
+                       out, out_stride, out_coff, out_f32, mk, mask_stride, mask_coff, vol, cin, flip, relu);
+}
+
+template <int NT>
+void launch_conv_nt(int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride,
+                    int in_coff, const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff,
+                    const uint16_t* mk, int mask_stride, int mask_coff, int cin, int flip, int relu) {
+    if (cin % 32 == 0)
+        launch_conv_t<NT, 32>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
+                              mask_stride, mask_coff, cin, flip, relu);
+    else if (cin % 16 == 0)
+        launch_conv_t<NT, 16>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
+                              mask_stride, mask_coff, cin, flip, relu);
+    else
+        launch_conv_t<NT, 8>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
+                             mask_stride, mask_coff, cin, flip, relu);
+}
+
+void launch_conv(int nt, int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride,
+                 int in_coff, const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff,
+                 const uint16_t* mk, int mask_stride, int mask_coff, int cin, int flip, int relu) {
+#define LC(N)                                                                                                     \
+    case N:                                                                                                       \
+        launch_conv_nt<N>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,         \
+                          mask_stride, mask_coff, cin, flip, relu);                                               \
+        break;
+    switch (nt) { LC(1) LC(2) LC(3) LC(4) LC(5) LC(6) LC(7) LC(8) }
+#undef LC
+}
+
+// Largest divisor of n that is at most 4: channel tiles per wave in the weight gradient.
+int tiles_per_wave(int n) {
+    for (int d = 4; d > 1; --d)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+template <int NB, int CB>
+void launch_wgrad_t(int nt, int ct, int nparts, hipStream_t s, const uint16_t* in, int in_stride, int in_coff,
+                    const uint16_t* dy, int dy_stride, int dy_coff, float* part, float* part_db, learn::Vol vol,
+                    int cin, int cout, int chunk) {
+    const int ncg = ct / CB;
+    hipLaunchKernelGGL((learn::wgrad_kernel<NB, CB>), dim3(nparts, 27, (nt / NB) * ncg), dim3(64), 0, s, in,
+                       in_stride, in_coff, dy, dy_stride, dy_coff, part, part_db, vol, cin, cout, chunk, ncg);
+}
+
+void launch_wgrad(int nt, int ct, int nparts, hipStream_t s, const uint16_t* in, int in_stride, int in_coff,
+                  const uint16_t* dy, int dy_stride, int dy_coff, float* part, float* part_db, learn::Vol vol,
+                  int cin, int cout, int chunk) {
+    const int nb = tiles_per_wave(nt), cb = tiles_per_wave(ct);
+#define LW(A, B)                                                                                             \
+    if (nb == A && cb == B) {                                                                                \
+        launch_wgrad_t<A, B>(nt, ct, nparts, s, in, in_stride, in_coff, dy, dy_stride, dy_coff, part, part_db, \
+                             vol, cin, cout, chunk);                                                         \
+        return;                                                                                              \
+    }
+    LW(1, 1) LW(1, 2) LW(1, 3) LW(1, 4) LW(2, 1) LW(2, 2) LW(2, 3) LW(2, 4)
+    LW(3, 1) LW(3, 2) LW(3, 3) LW(3, 4) LW(4, 1) LW(4, 2) LW(4, 3) LW(4, 4)
+#undef LW
+}
 }  // namespace
 
 extern "C" {
@@ -432,17 +575,13 @@ int das_conv3d(const void* in, int in_stride, int in_coff, const void* weight, c
     if (!al(in, 16) || !al(weight, 16)) return lfail(DAS_EALIGN, "conv3d: input and weights must be 16-byte aligned");
     const int64_t V = (int64_t)D * H * W;
     const learn::Vol vol{D, H, W};
-    const dim3 grid(blocks_for(V, 64)), block(256);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const uint16_t* x = reinterpret_cast<const uint16_t*>(in);
     const uint16_t* w = reinterpret_cast<const uint16_t*>(weight);
     const uint16_t* mk = reinterpret_cast<const uint16_t*>(mask);
-    if (out_f32)
-        hipLaunchKernelGGL(learn::conv3d_kernel<true>, grid, block, 0, s, x, in_stride, in_coff, w, bias, out,
-                           out_stride, out_coff, mk, mask_stride, mask_coff, vol, cin, cout, flip, relu);
-    else
-        hipLaunchKernelGGL(learn::conv3d_kernel<false>, grid, block, 0, s, x, in_stride, in_coff, w, bias, out,
-                           out_stride, out_coff, mk, mask_stride, mask_coff, vol, cin, cout, flip, relu);
+    (void)V;
+    launch_conv(cout / 16, out_f32 != 0, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
+                mask_stride, mask_coff, cin, flip, relu);
     return launch_status("conv3d launch failed");
 }
 
@@ -455,15 +594,18 @@ int das_conv3d_wgrad(const void* in, int in_stride, int in_coff, const void* dy,
     const int64_t V = (int64_t)D * H * W;
     const int nparts = (int)((V + chunk - 1) / chunk);
     const int64_t K = 27LL * cin, nw = (int64_t)cout * K;
-    if (in_stride < in_coff + cin || in_coff < 0 || dy_stride < dy_coff + cout || dy_coff < 0)
-        return lfail(DAS_ESHAPE, "wgrad: channel slice outside its buffer");
+    if (in_stride < in_coff + cin || in_coff < 0 || dy_stride < dy_coff + cout || dy_coff < 0 || in_stride % 8 ||
+        in_coff % 8 || dy_stride % 8 || dy_coff % 8)
+        return lfail(DAS_ESHAPE, "wgrad: channel slices outside their buffers or not multiples of 8");
+    if ((int64_t)D * H * W >= (int64_t)1 << 31) return lfail(DAS_ESHAPE, "wgrad: volume above 2^31 voxels");
+    if (!al(in, 16) || !al(dy, 16)) return lfail(DAS_EALIGN, "wgrad: input and dy must be 16-byte aligned");
     if (work_floats < (int64_t)nparts * (nw + cout)) return lfail(DAS_ESHAPE, "wgrad: work buffer too small");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float* part = work;
     float* part_db = work + (int64_t)nparts * nw;
-    hipLaunchKernelGGL(learn::wgrad_kernel, dim3(nparts), dim3(256), 0, s, reinterpret_cast<const uint16_t*>(in),
-                       in_stride, in_coff, reinterpret_cast<const uint16_t*>(dy), dy_stride, dy_coff, part, part_db,
-                       learn::Vol{D, H, W}, cin, cout, chunk);
+    launch_wgrad(cout / 16, (cin + 15) / 16, nparts, s, reinterpret_cast<const uint16_t*>(in), in_stride, in_coff,
+                 reinterpret_cast<const uint16_t*>(dy), dy_stride, dy_coff, part, part_db, learn::Vol{D, H, W}, cin,
+                 cout, chunk);
     hipLaunchKernelGGL(learn::reduce_parts_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, s, part, nparts, nw,
                        dw);
     hipLaunchKernelGGL(learn::reduce_parts_kernel, dim3(blocks_for(cout, 256)), dim3(256), 0, s, part_db, nparts,

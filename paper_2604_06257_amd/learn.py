@@ -218,8 +218,8 @@ class UNet:
 
     @staticmethod
     def _chunk(v):
-        """Voxels per weight-gradient partial sum: about 512 partial sums, at least 32 voxels each."""
-        return max(32, ((v + 511) // 512 + 31) // 32 * 32)
+        """Voxels per weight-gradient partial sum: at most 256 partial sums, at least 1024 voxels each."""
+        return max(1024, ((v + 255) // 256 + 31) // 32 * 32)
 
     # -- parameters
     def w(self, name, dtype="bf16"):
