@@ -137,6 +137,42 @@ def time_steps(plan, iq, out, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def time_launches(plan, iq, out, repeats, torch, flush=None):
+    """Per-launch kernel times (HIP events around each launch on the launch stream): (median, min) in ms.
+
+    With ``flush`` (a 1 GiB device buffer) the buffer is rewritten before every launch so that the
+    launch starts with cold caches (L2 and the 256 MB Infinity Cache evicted)."""
+    stream = torch.cuda.current_stream()
+    times = []
+    plan.execute(iq, out)
+    for _ in range(repeats):
+        if flush is not None:
+            flush.fill_(1.0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.execute(iq, out)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2], times[0]
+
+
+def iq16_range(iq):
+    """Largest |component| of complex64 IQ and the fraction of nonzero components that are subnormal
+    when stored as float16 / bfloat16 (round to nearest even; overflow needs max >= 65504 for float16)."""
+    ri = np.abs(np.stack([iq.real, iq.imag]).ravel().astype(np.float32))
+    nz = ri[ri > 0]
+    f16 = np.abs(nz.astype(np.float16).astype(np.float32))
+    sub16 = float(np.mean((f16 > 0) & (f16 < 2.0 ** -14))) if nz.size else 0.0
+    # bfloat16 keeps float32's exponent range: subnormal below 2^-126
+    subbf = float(np.mean(nz < 2.0 ** -126)) if nz.size else 0.0
+    return {"max_abs_component": float(ri.max()) if ri.size else 0.0, "fits_fp16": bool(ri.max() < 65504.0),
+            "fp16_subnormal_fraction": sub16, "bf16_subnormal_fraction": subbf,
+            "fp16_flushed_to_zero_fraction": float(np.mean(f16 == 0)) if nz.size else 0.0}
+
+
 def scaling_sweep(axis, steps, warmup):
     """Throughput while one size varies around the rotating-disk stand-in (paper Sec. 4.5, Fig. 5):
     voxels 63k-6.3M (finer grids over the same region), elements 128-8192 (same aperture), frames 1-512.
@@ -226,6 +262,10 @@ def main():
     out = torch.empty((V, F), dtype=torch.complex64, device="cuda")
     ms, wall = time_steps(plan, iq, out, args.steps, args.warmup, torch)
     value = points / (ms * 1e-3)
+    warm_med, warm_min = time_launches(plan, iq, out, 51, torch)
+    flush = torch.empty((1 << 30) // 4, dtype=torch.float32, device="cuda")
+    cold_med, cold_min = time_launches(plan, iq, out, 21, torch, flush=flush)
+    del flush
 
     active_pts = info["active_triples"] * F
     achieved_tflops = active_pts * FLOP_PER_POINT / (ms * 1e-3) / 1e12
@@ -246,6 +286,9 @@ def main():
                    "transmits": T, "frames": F, "samples": S, "points_per_step": points, "iq": "complex64",
                    "parallelism": "single GPU"},
         "wall_ms_per_step": wall * 1e3 / args.steps,
+        "per_launch_ms": {"warm_median": warm_med, "warm_min": warm_min, "cold_median": cold_med,
+                          "cold_min": cold_min, "cold_points_per_s": points / (cold_med * 1e-3),
+                          "cold": "1 GiB buffer rewritten before each launch (L2 and Infinity Cache evicted)"},
         "active_points_per_s": active_pts / (ms * 1e-3),
         "active_fraction": info["active_triples"] / max(1, info["total_triples"]),
         "processed_fraction": info["processed_triples"] / max(1, info["total_triples"]),
@@ -277,6 +320,7 @@ def main():
                 v["nrmse_db_vs_fp64"] = oracle.nrmse_db(y16[:ref.shape[0]], ref)
             var[name] = v
             del iq16
+        var["iq_range"] = iq16_range(iq_np)
         result["iq16_variants"] = var
     if args.copy_calibration > 0:
         n = int(args.copy_calibration * (1 << 30)) // 4

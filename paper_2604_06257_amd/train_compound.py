@@ -1,12 +1,13 @@
 """Train and evaluate learned compounding on seeded synthetic phantoms.
 
-    python -m paper_2604_06257_amd.train_compound --geometry c5 --n-train 1900 --n-test 100 --steps 6000
+    python -m paper_2604_06257_amd.train_compound --geometry c5 --n-train 1800 --n-val 100 --n-test 100 --steps 12000
 
-Data: per phantom (seed base + i) the GPU echo simulator writes the IQ of all
+Data: per phantom (seed base + i; training, validation and test phantoms in
+that order) the GPU echo simulator writes the IQ of all
 plane waves, the library beamforms the full compound (the target) and the
 input angles one by one; features are normalised by the RMS of the
 input-angle sum.  Everything stays in device memory.  Training is Adam on one
-volume per step; evaluation reports the normalised RMS error in dB against
+volume per step; the validation set picks the checkpoint; evaluation reports the normalised RMS error in dB against
 the full compound for the scaled few-angle sum (no network) and for the
 network, and the speedup t(full) / (t(input angles) + t(features) +
 t(network) + t(output)).
@@ -159,14 +160,19 @@ def run(args, log=print):
                          p["tukey_alpha"])
     lc = LearnedCompounding(params, elem, vox, tx, geo["dims"], geo["input_idx"])
     lc.net.init_params(seed=args.seed)
+    n_val = getattr(args, "n_val", 0)
+    eval_every = getattr(args, "eval_every", 0) or args.steps
     t0 = time.time()
     train = Dataset(lc, geo, args.n_train, first=0, log=log)
-    test = Dataset(lc, geo, args.n_test, first=args.n_train, log=log)
+    val = Dataset(lc, geo, n_val, first=args.n_train, log=log) if n_val > 0 else None
+    test = Dataset(lc, geo, args.n_test, first=args.n_train + n_val, log=log)
     t_data = time.time() - t0
-    log("data: %d train + %d test phantoms in %.1f s" % (args.n_train, args.n_test, t_data))
+    log("data: %d train + %d validation + %d test phantoms in %.1f s" % (args.n_train, n_val, args.n_test, t_data))
     base_db, net0_db = evaluate(lc, test)
     log("before training: baseline %.2f dB, network %.2f dB" % (base_db, net0_db))
     order = np.random.default_rng(args.seed).permutation(args.n_train)
+    best = None  # (validation dB, step, master weights) of the best checkpoint
+    val_curve = []
     t0 = time.time()
     run_loss = 0.0
     for step in range(args.steps):
@@ -178,15 +184,25 @@ def run(args, log=print):
             run_loss = float(parts.sum()) / (2 * V)
             log("step %d/%d loss %.4e lr %.2e (%.1f s)" % (step + 1, args.steps, run_loss,
                                                           lr_at(step, args.steps, args.lr), time.time() - t0))
+        if val is not None and ((step + 1) % eval_every == 0 or step + 1 == args.steps):
+            vdb = evaluate(lc, val)[1]
+            val_curve.append((step + 1, round(vdb, 3)))
+            log("step %d validation network %.3f dB" % (step + 1, vdb))
+            if best is None or vdb < best[0]:
+                best = (vdb, step + 1, lc.net.master.clone())
     torch.cuda.synchronize()
     t_train = time.time() - t0
+    if best is not None:  # the checkpoint with the lowest validation error
+        lc.net.master.copy_(best[2])
+        lc.net.refresh_copies()
     base_db, net_db = evaluate(lc, test)
     train_base_db, train_net_db = evaluate(lc, train) if args.n_train <= 200 else (None, None)
     times = time_paths(lc, geo)
     speedup = times["full_das"] / times["learned_total"]
     res = {"geometry": args.geometry, "dims": list(geo["dims"]), "n_elem": E, "n_angles": T,
            "input_angles_deg": [round(float(geo["angles"][t, 1]) / DEG, 3) for t in geo["input_idx"]],
-           "n_train": args.n_train, "n_test": args.n_test, "steps": args.steps, "lr": args.lr,
+           "n_train": args.n_train, "n_val": n_val, "n_test": args.n_test, "steps": args.steps, "lr": args.lr,
+           "validation_nrmse_db": val_curve, "checkpoint_step": best[1] if best is not None else args.steps,
            "test_nrmse_db": {"scaled_input_sum": round(base_db, 3), "network": round(net_db, 3),
                              "network_untrained": round(net0_db, 3)},
            "gain_db": round(base_db - net_db, 3),
@@ -204,9 +220,11 @@ def run(args, log=print):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--geometry", default="c5", choices=("c5", "small"))
-    ap.add_argument("--n-train", type=int, default=1900)
+    ap.add_argument("--n-train", type=int, default=1800)
+    ap.add_argument("--n-val", type=int, default=100)
     ap.add_argument("--n-test", type=int, default=100)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--eval-every", type=int, default=2000, help="validation interval in steps")
+    ap.add_argument("--steps", type=int, default=12000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--log-every", type=int, default=500)

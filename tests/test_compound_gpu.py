@@ -93,7 +93,8 @@ def test_full_compound_is_the_sum_of_single_angle_volumes():
 
 def test_learned_compounding_beats_scaled_input_sum():
     from paper_2604_06257_amd.train_compound import run
-    args = types.SimpleNamespace(geometry="small", n_train=48, n_test=8, steps=600, lr=2e-3, seed=0, log_every=200)
+    args = types.SimpleNamespace(geometry="small", n_train=48, n_val=4, n_test=8, steps=600, lr=2e-3, seed=0,
+                                 log_every=200, eval_every=200)
     res = run(args, log=print)
     print(res)
     nr = res["test_nrmse_db"]

@@ -260,3 +260,32 @@ def test_16bit_iq_parity_and_storage_error(kind):
     db = oracle.nrmse_db(y[idx], ref)
     print(kind, "storage error vs complex64 input: %.1f dB" % db)
     assert db <= (-65.0 if kind == "f16" else -45.0)
+
+
+def test_one_plan_on_two_streams_concurrently():
+    """The plan is immutable: executing it on two streams at once gives the same bits as one at a time."""
+    cfg = make_config("c2", with_iq=False, n_frames=8)
+    p = cfg["params"]
+    E, S = 128, p["n_samples"]
+    iqa = random_iq((1, E, S, 8), seed=41)
+    iqb = random_iq((1, E, S, 8), seed=42)
+    tx = tx_table(cfg["vox"], cfg["angles"], p["c"])
+    params = das.Params(1, E, S, 8, cfg["vox"].shape[0], p["c"], p["fs"], p["fd"], p["t0"], p["f_number"],
+                        p["tukey_alpha"])
+    with das.Plan(params, dev(cfg["elem"]), dev(cfg["vox"]), dev(tx)) as plan:
+        a, b = dev(iqa), dev(iqb)
+        ya, yb = plan.execute(a), plan.execute(b)
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        outs = []
+        for _ in range(3):
+            oa = torch.empty_like(ya)
+            ob = torch.empty_like(yb)
+            s1.wait_stream(torch.cuda.current_stream())
+            s2.wait_stream(torch.cuda.current_stream())
+            plan.execute(a, out=oa, stream=s1)
+            plan.execute(b, out=ob, stream=s2)
+            outs.append((oa, ob))
+        torch.cuda.synchronize()
+        for oa, ob in outs:
+            assert torch.equal(oa, ya) and torch.equal(ob, yb)
