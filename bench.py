@@ -231,7 +231,7 @@ def main():
         scaling_sweep(args.sweep, args.steps, args.warmup)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build's path runs on a single MI355X "
+        print("bench.py measures one GPU only: the beamforming path runs on a single MI355X "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
