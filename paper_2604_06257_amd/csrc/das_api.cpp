@@ -453,6 +453,37 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
             }
         }
         off[tl.n_tiles] = (int32_t)items.size();
+        if (das::stage_pairs(var.fc)) {
+            // Stages: consecutive items of a tile whose windows fit one LDS buffer together (at most pitch - 1
+            // rows) share a stage, i.e. one fill and one barrier.  Two int4 per stage; an absent second item
+            // has zero rows.  DAS_PAIR=0 keeps one item per stage (same layout).  Variants that do not pair
+            // keep one int4 per item.
+            const char* pair_env = std::getenv("DAS_PAIR");
+            const bool pair = !(pair_env != nullptr && std::strcmp(pair_env, "0") == 0);
+            const int slack = das::fill_rows_per_thread(var.fc, var.pitch) - 1;
+            std::vector<int4> stages;
+            std::vector<int32_t> soff((size_t)tl.n_tiles + 1, 0);
+            for (int64_t t = 0; t < tl.n_tiles; ++t) {
+                soff[t] = (int32_t)(stages.size() / 2);
+                for (int32_t i = off[t]; i < off[t + 1];) {
+                    const int4 a = items[(size_t)i];
+                    // the second window starts at a multiple of the fill rows per thread (at most
+                    // slack + 1): reserve the slack
+                    if (pair && i + 1 < off[t + 1] && a.w + slack + items[(size_t)i + 1].w <= rows) {
+                        stages.push_back(a);
+                        stages.push_back(items[(size_t)i + 1]);
+                        i += 2;
+                    } else {
+                        stages.push_back(a);
+                        stages.push_back(make_int4(0, 0, 0, 0));
+                        i += 1;
+                    }
+                }
+            }
+            soff[tl.n_tiles] = (int32_t)(stages.size() / 2);
+            items.swap(stages);
+            off.swap(soff);
+        }
         const int chunks = (p->n_frames + var.fc - 1) / var.fc;
         const char* ord = std::getenv("DAS_ORDER");
         const std::vector<int32_t> order =

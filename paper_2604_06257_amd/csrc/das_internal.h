@@ -38,8 +38,10 @@ struct PlanDev {
     int32_t* slot_vox = nullptr;  // [n_slots]
     float* elem = nullptr;     // [E][3]
     int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows); plan-time only
-    int4* items = nullptr;      // per tile, the (t, e, first row, rows) work items, e-major
-    int32_t* item_off = nullptr;  // [n_tiles + 1] offsets into items
+    int4* items = nullptr;      // per tile, the (t, e, first row, rows) work items, e-major, in stages:
+                                // two int4 per stage for variants that pair (the second may be empty:
+                                // rows = 0), one otherwise
+    int32_t* item_off = nullptr;  // [n_tiles + 1] offsets into items, in stages
     int32_t* wg_unit = nullptr;   // [n_tiles * chunks] workgroup -> tile * chunks + frame chunk
     int32_t fc = 0, pitch = 0, groups = 1;  // kernel variant: frames per workgroup, LDS row pitch, element groups
 };
@@ -54,6 +56,17 @@ struct Variant {
     int fc, pitch, groups;
 };
 Variant choose_variant(int frames, int max_window, int64_t n_tiles);
+
+// Whether a variant stages two items per step (the plan packs stages only for such variants): with 8 or
+// more frames per workgroup the saved fill and barrier outweigh the extra registers.
+constexpr bool stage_pairs(int fc) { return fc >= 8; }
+
+// Window rows each fill thread stages for a variant (the largest over the IQ types: complex64, which packs
+// the fewest frames into a 16-byte load); the second window of a stage starts at a multiple of it.
+constexpr int fill_rows_per_thread(int fc, int pitch) {
+    const int fpt = fc < 2 ? fc : 2;
+    return ((pitch - 1) * (fc / fpt) + kSlots - 1) / kSlots;
+}
 
 // Computes per (tile, transmit, element) sample windows and counts.
 // counts[0] = active (slot, e, t) triples (w > 0, inside the record);

@@ -8,7 +8,9 @@
 //       sample row i0, weight beta, complex C = w exp(+j 2 pi fd tau)
 //     the workgroup stages the tile's sample window of channel data into LDS
 //       as rows (q[s], q[s+1] - q[s]) for each of the FC frames, frame-major,
-//       zero outside the record (interpolation is then one FMA per part)
+//       zero outside the record (interpolation is then one FMA per part);
+//       with 8 or more frames per workgroup two such windows share one stage
+//       (one fill, one barrier) when their rows fit the buffer together
 //     every active lane, for each frame f:
 //       (q0, d) = lds[f][i0 - lo]         one ds_read_b128
 //       acc[f] += C * (q0 + beta d)       six FP32 FMAs
@@ -159,11 +161,14 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 // rows of its frames (each sample once) with 16-byte loads when aligned.
 // Waves per SIMD that the LDS footprint allows (the compiler may then spend
 // registers on instruction-level parallelism instead of occupancy).
+// Variants that stage two items per step are capped so that the second item's registers (coefficients,
+// transmit time) fit without spilling: 4 waves (128 VGPRs) up to 16 frames, 3 (168) for 32.
 template <int FC, int P, int G>
 constexpr int das_waves_per_simd() {
     constexpr int bytes = G * 2 * FC * P * 16;
     constexpr int wgs = (160 * 1024) / bytes;
-    return (wgs * G) < 1 ? 1 : ((wgs * G) > 8 ? 8 : wgs * G);
+    constexpr int cap = !stage_pairs(FC) ? 8 : (FC >= 32 ? 3 : 4);
+    return (wgs * G) < 1 ? 1 : ((wgs * G) > cap ? cap : wgs * G);
 }
 
 template <int FC, int P, int DT, int G>
@@ -203,59 +208,78 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
         acc_i[f] = 0.0f;
     }
     const int first = p.item_off[tile];
-    const int nitems = p.item_off[tile + 1] - first;
-    const int4* items = p.items + first;
+    const int nitems = p.item_off[tile + 1] - first;  // stages of this tile
+    // two items per stage (the second may be empty) for variants that pair, else one
+    constexpr int kIS = stage_pairs(FC) ? 2 : 1;
+    const int4* items = p.items + kIS * (int64_t)first;
     const int nsteps = (nitems + G - 1) / G;
 
     // Channel data of one (t, e) record through a buffer resource: offsets
     // outside [0, S * F) samples (rows before 0 or past S - 1) read as zero,
     // which is the zero padding of the record.
     const int64_t rec_bytes = (int64_t)kp.S * kp.F * kEB;
-    const int lane_off = (row0 * kp.F + fbase) * kEB;  // this thread's first row and frames
+    const int lane_off = fbase * kEB;  // this thread's frames within a row
     const int row_bytes = kp.F * kEB;
     const bool fill_frames = fbase < kp.F;
-    auto load_item = [&](int k, Raw (&raw)[RPT + 1], float& txv, int4& it) {
-        it = items[k];
-        txv = p.tx[(int64_t)it.x * kp.n_slots + slot];
+    auto rsrc = [&](const int4& it) {
         const char* rec = reinterpret_cast<const char*>(iq) + ((int64_t)it.x * kp.E + it.y) * rec_bytes;
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
-        const int off0 = it.z * row_bytes + lane_off;
-        if (row0 < it.w && full_frames) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
+    };
+    auto load_raw = [&](const __amdgpu_buffer_rsrc_t& rs, int off, Raw& dst) {
+        if (full_frames) {
+            if constexpr (sizeof(Raw) == 16) {
+                dst = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+            } else if constexpr (sizeof(Raw) == 8) {
+                dst = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+            } else {
+                dst = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+            }
+        } else {
+            // unaligned rows or the last partial frame group: one sample at a time
+            uint32_t* w = reinterpret_cast<uint32_t*>(&dst);
 #pragma unroll
-            for (int j = 0; j <= RPT; ++j) {
-                const int off = off0 + j * row_bytes;
-                if constexpr (sizeof(Raw) == 16) {
-                    raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-                } else if constexpr (sizeof(Raw) == 8) {
-                    raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+            for (int q = 0; q < FPT; ++q) {
+                if (kEB == 8) {
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + q * 8, 0, 0);
+                    w[2 * q] = (uint32_t)v[0];
+                    w[2 * q + 1] = (uint32_t)v[1];
                 } else {
-                    raw[j] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                    w[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + q * 4, 0, 0);
                 }
             }
-        } else if (row0 < it.w && fill_frames) {
-            // unaligned rows or the last partial frame group: one sample at a time
+        }
+    };
+    // Stage rows 0 .. a.w - 1 are item a's window; item b's window starts at row bb(a) = a.w rounded up to a
+    // multiple of RPT, so the RPT rows of a fill thread (and the sample after them) come from one record.
+    auto bbase = [&](const int4& ia) { return (ia.w + RPT - 1) / RPT * RPT; };
+    auto load_item = [&](int k, Raw (&raw)[RPT + 1], float& txa, float& txb, int4& ia, int4& ib) {
+        ia = items[kIS * k];
+        // without stage pairing the second item is a constant empty one and its code folds away
+        ib = stage_pairs(FC) ? items[kIS * k + 1] : make_int4(0, 0, 0, 0);
+        txa = p.tx[(int64_t)ia.x * kp.n_slots + slot];
+        txb = ib.w > 0 ? p.tx[(int64_t)ib.x * kp.n_slots + slot] : 0.0f;
+        const int bb = bbase(ia);
+        const bool in_b = ib.w > 0 && row0 >= bb;
+        if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
+            const int4& it = in_b ? ib : ia;
+            const int r0 = in_b ? row0 - bb : row0;
+            // the record is uniform per thread but not per wave: two resources, each wave-uniform
+            const __amdgpu_buffer_rsrc_t ra = rsrc(ia);
+            const __amdgpu_buffer_rsrc_t rb = rsrc(ib.w > 0 ? ib : ia);
 #pragma unroll
             for (int j = 0; j <= RPT; ++j) {
-                const int off = off0 + j * row_bytes;
-                uint32_t* w = reinterpret_cast<uint32_t*>(&raw[j]);
-#pragma unroll
-                for (int q = 0; q < FPT; ++q) {
-                    if (kEB == 8) {
-                        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + q * 8, 0, 0);
-                        w[2 * q] = (uint32_t)v[0];
-                        w[2 * q + 1] = (uint32_t)v[1];
-                    } else {
-                        w[q] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + q * 4, 0, 0);
-                    }
-                }
+                const int off = (it.z + r0 + j) * row_bytes + lane_off;
+                if (in_b) load_raw(rb, off, raw[j]);
+                else load_raw(ra, off, raw[j]);
             }
         }
     };
     // LDS frame slot of frame f: frames of one fill thread go to slots NFG
     // apart, so the 16 lanes of a write hit 16 different bank groups.
-    auto store_item = [&](const int4& it, const Raw (&raw)[RPT + 1], float4* buf) {
-        if (row0 < it.w && fill_frames) {
+    auto store_item = [&](const int4& ia, const int4& ib, const Raw (&raw)[RPT + 1], float4* buf) {
+        const int bb = bbase(ia);
+        const bool in_b = ib.w > 0 && row0 >= bb;
+        if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
 #pragma unroll
@@ -268,17 +292,17 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
     };
     // Coefficients of an item for this lane; lanes outside the aperture, the
     // record or the item's window get zero weights and row 0 (so the MAC runs
-    // without branches and adds exact zeros).
+    // without branches and adds exact zeros).  base = the item's first stage row.
     int last_e = -1;
     das_rx rx;
-    auto coef_item = [&](const int4& it, float txv, bool live) {
+    auto coef_item = [&](const int4& it, float txv, bool live, int base) {
         if (it.y != last_e) {
             rx = das_rx_setup(vx, vy, vz, p.elem[3 * it.y], p.elem[3 * it.y + 1], p.elem[3 * it.y + 2], kp);
             last_e = it.y;
         }
         das_coef c = das_tx_setup(rx, txv, kp);
         const bool use = live && (vox >= 0) && c.active && c.i0 >= it.z && c.i0 < it.z + it.w;
-        c.row = use ? c.i0 - it.z : 0;
+        c.row = use ? c.i0 - it.z + base : 0;
         c.beta = use ? c.beta : 0.0f;
         c.cr = use ? c.cr : 0.0f;
         c.ci = use ? c.ci : 0.0f;
@@ -298,37 +322,59 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
         }
     };
 
-    // Step s of this group handles item k_s = s * G + grp.  Registers of stage
-    // s % 2 hold the window, transmit time and item of k_s (loaded at step
+    // Step s of this group handles stage k_s = s * G + grp.  Registers of pipeline
+    // slot s % 2 hold the window, transmit times and items of k_s (loaded at step
     // s - 2); coefficients of k_s were formed during step s - 1.
-    // Both window buffers start zeroed, so a step without an item (its
+    // Both window buffers start zeroed, so a step without a stage (its
     // coefficients are zero) multiplies zeros, never stale or unset LDS.
     for (int i = gt; i < 2 * kBuf; i += kSlots) buf0[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     __syncthreads();
     Raw ra[RPT + 1], rb[RPT + 1];
-    float txa = 0.0f, txb = 0.0f;
-    int4 ita = make_int4(0, 0, 0, 0), itb = make_int4(0, 0, 0, 0);
-    if (grp < nitems) load_item(grp, ra, txa, ita);
-    if (grp + G < nitems) load_item(grp + G, rb, txb, itb);
-    das_coef cc = coef_item(ita, txa, grp < nitems);
+    float txa0 = 0.0f, txa1 = 0.0f, txb0 = 0.0f, txb1 = 0.0f;
+    const int4 z4 = make_int4(0, 0, 0, 0);
+    int4 ia0 = z4, ia1 = z4, ib0 = z4, ib1 = z4;  // items (first, second) of pipeline slots a and b
+    if (grp < nitems) load_item(grp, ra, txa0, txa1, ia0, ia1);
+    if (grp + G < nitems) load_item(grp + G, rb, txb0, txb1, ib0, ib1);
+    // the second item's coefficients only when the stage has one (a wave-uniform branch; an empty item
+    // must not evict the cached receive geometry)
+    das_coef none;
+    none.i0 = 0;
+    none.row = 0;
+    none.beta = none.cr = none.ci = 0.0f;
+    none.active = false;
+    das_coef c0 = coef_item(ia0, txa0, grp < nitems, 0);
+    das_coef c1 = (grp < nitems && ia1.w > 0) ? coef_item(ia1, txa1, true, bbase(ia0)) : none;
+    bool two = grp < nitems && ia1.w > 0;
     for (int step = 0; step < nsteps; step += 2) {
         {
             const int k = step * G + grp;
-            if (k < nitems) store_item(ita, ra, buf0);
+            if (k < nitems) store_item(ia0, ia1, ra, buf0);
             __syncthreads();
-            if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa, ita);
-            const das_coef cn = coef_item(itb, txb, k + G < nitems);  // item k + G
-            mac_item(cc, buf0);
-            cc = cn;
+            if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa0, txa1, ia0, ia1);
+            const bool live = k + G < nitems;
+            const das_coef n0 = coef_item(ib0, txb0, live, 0);  // stage k + G
+            const bool ntwo = live && ib1.w > 0;
+            const das_coef n1 = ntwo ? coef_item(ib1, txb1, true, bbase(ib0)) : none;
+            mac_item(c0, buf0);
+            if (two) mac_item(c1, buf0);
+            c0 = n0;
+            c1 = n1;
+            two = ntwo;
         }
         if (step + 1 < nsteps) {
             const int k = (step + 1) * G + grp;
-            if (k < nitems) store_item(itb, rb, buf1);
+            if (k < nitems) store_item(ib0, ib1, rb, buf1);
             __syncthreads();
-            if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb, itb);
-            const das_coef cn = coef_item(ita, txa, k + G < nitems);  // item k + G
-            mac_item(cc, buf1);
-            cc = cn;
+            if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb0, txb1, ib0, ib1);
+            const bool live = k + G < nitems;
+            const das_coef n0 = coef_item(ia0, txa0, live, 0);  // stage k + G
+            const bool ntwo = live && ia1.w > 0;
+            const das_coef n1 = ntwo ? coef_item(ia1, txa1, true, bbase(ia0)) : none;
+            mac_item(c0, buf1);
+            if (two) mac_item(c1, buf1);
+            c0 = n0;
+            c1 = n1;
+            two = ntwo;
         }
     }
     if (G > 1) {
