@@ -46,8 +46,8 @@ int das_conv3d(const void *in, int in_stride, int in_coff, const void *weight, c
 /* Weight and bias gradients of the (unflipped) convolution:
  *   dw[n][tap][c] = sum_v dy[v][n] * in[v + off(tap)][c],  db[n] = sum_v dy[v][n]
  * (float32 outputs, MFMA with FP32 accumulation) split over voxel chunks of
- * `chunk` voxels (a multiple of 32) whose partial sums are added in chunk order
- * (deterministic).  `work` holds das_conv3d_wgrad_work(...) floats.  Cin a
+ * `chunk` voxels (a multiple of 32) whose partial sums are added in a fixed
+ * order (parts r, r + 8, ... for r < 8, then the 8 sums in order: deterministic).  `work` holds das_conv3d_wgrad_work(...) floats.  Cin a
  * multiple of 8, Cout of 16; strides and channel offsets of in and dy multiples
  * of 8, both 16-byte aligned; fewer than 2^31 voxels. */
 int das_conv3d_wgrad(const void *in, int in_stride, int in_coff, const void *dy, int dy_stride, int dy_coff,

@@ -34,9 +34,9 @@ struct Vol {
 
 constexpr int kMaxNT = 8;  // up to 128 output channels per launch
 
-// Convolution on a brick of 8 (W) x 8 (H) x MT (D) output voxels per workgroup of 4 waves.  Wave w owns the
-// 4 x 4 (W x H) patch w of every depth slice (one 16-voxel MFMA row tile per slice) and NT x 16 output
-// channels.  The input brick with its one-voxel halo, 10 x 10 x (MT + 2) voxels, is staged in LDS one
+// Convolution on a brick of 8 (W) x 8 (H) x MT (D) output voxels per workgroup of 4 waves, for NT x 16 of the
+// output channels (grid.y = channel groups).  Wave w owns the 4 x 4 (W x H) patch w of every depth slice (one
+// 16-voxel MFMA row tile per slice) and the workgroup's output channels.  The input brick with its one-voxel halo, 10 x 10 x (MT + 2) voxels, is staged in LDS one
 // channel chunk (CC channels) at a time, so each input value is read from global memory once per chunk
 // instead of once per tap; the operand-A fragments of all 27 taps are then 16-byte LDS reads.  Weights
 // (operand B) come from global memory (shared by all waves through the caches), one K step ahead.
@@ -56,6 +56,8 @@ __global__ __launch_bounds__(256) void conv3d_kernel(const uint16_t* __restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nbw = (vol.W + 7) / 8, nbh = (vol.H + 7) / 8;
     const int bx = blockIdx.x % nbw, by = (blockIdx.x / nbw) % nbh, bz = blockIdx.x / (nbw * nbh);
+    // output channels [n0, n0 + 16 NT) of this workgroup (grid.y = channel groups)
+    const int n0 = blockIdx.y * NT * 16;
     const int w0 = 8 * bx, h0 = 8 * by, d0 = MT * bz;
     const int K = 27 * Cin;
     const int s = flip ? -1 : 1;
@@ -85,27 +87,29 @@ __global__ __launch_bounds__(256) void conv3d_kernel(const uint16_t* __restrict_
         bf16x8 b[NT], bn[NT];
         auto load_b = [&](int ks, bf16x8(&dst)[NT]) {
             const int kl = 32 * ks + 8 * g, tap = kl / CC, c = kl - tap * CC;
+            const uint16_t* wp = wk + (int64_t)(n0 + (lane & 15)) * K + tap * Cin + cc0 + c;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 dst[t] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                if (tap < 27)
-                    dst[t] = *reinterpret_cast<const bf16x8*>(wk + (int64_t)(t * 16 + (lane & 15)) * K + tap * Cin +
-                                                             cc0 + c);
+                if (tap < 27) dst[t] = *reinterpret_cast<const bf16x8*>(wp + (int64_t)t * 16 * K);
             }
         };
         load_b(0, b);
         for (int ks = 0; ks < KSTEPS; ++ks) {
             if (ks + 1 < KSTEPS) load_b(ks + 1, bn);
-            const int kl = 32 * ks + 8 * g, tap = kl / CC, c = kl - tap * CC;
-            const int dz = s * (tap / 9 - 1), dyy = s * ((tap / 3) % 3 - 1), dx = s * (tap % 3 - 1);
+            // operand A: this lane's halo voxel for depth slice 0 shifted by the tap, channel c; the other
+            // depth slices are whole halo planes (kHaloW * kHaloH voxels) further on
+            const int kl = 32 * ks + 8 * g, tap0 = kl / CC, c = kl - tap0 * CC;
+            const bool kin = tap0 < 27;
+            const int tap = kin ? tap0 : 13;  // padding steps past the last tap read nothing
+            const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int hv0 = ((1 + s * dz) * kHaloH + (rh + 1 + s * dyy)) * kHaloW + (rw + 1 + s * dx);
+            const uint16_t* ap = &halo[hv0 * VP + c];
             bf16x8 a[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 a[m] = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                if (tap < 27) {
-                    const int hv = ((m + 1 + dz) * kHaloH + (rh + 1 + dyy)) * kHaloW + (rw + 1 + dx);
-                    a[m] = *reinterpret_cast<const bf16x8*>(&halo[hv * VP + c]);
-                }
+                if (kin) a[m] = *reinterpret_cast<const bf16x8*>(ap + m * kHaloW * kHaloH * VP);
             }
 #pragma unroll
             for (int m = 0; m < MT; ++m)
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(256) void conv3d_kernel(const uint16_t* __restrict_
     // result rows 4 (lane / 16) + r of the tile: voxel (pw + r, ph + lane / 16) of the patch
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const int n = t * 16 + (lane & 15);
+        const int n = n0 + t * 16 + (lane & 15);
         const float bn_ = bias ? bias[n] : 0.0f;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
@@ -232,13 +236,24 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const uint16_t* __restrict__ 
     if (do_db && lane < NB * 16) part_db[(int64_t)b * Cout + n0 + lane] = dbs;
 }
 
-// dw[i] = sum_b part[b][i] in chunk order (deterministic), i over Cout * K; same for db.
-__global__ void reduce_parts_kernel(const float* __restrict__ part, int nparts, int64_t n, float* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// dw[i] = sum_b part[b][i], i over Cout * K (same for db): 32 outputs per workgroup, the parts split over 8
+// thread rows (row r sums parts r, r + 8, ... in order), the 8 row sums added in row order: deterministic.
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restrict__ part, int nparts, int64_t n,
+                                                           float* __restrict__ out) {
+    __shared__ float red[8][32];
+    const int col = threadIdx.x & 31, row = threadIdx.x >> 5;
+    const int64_t i = (int64_t)blockIdx.x * 32 + col;
     float s = 0.0f;
-    for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * n + i];
-    out[i] = s;
+    if (i < n)
+        for (int b = row; b < nparts; b += 8) s += part[(int64_t)b * n + i];
+    red[row][col] = s;
+    __syncthreads();
+    if (row == 0 && i < n) {
+        float t = red[0][col];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) t += red[r][col];
+        out[i] = t;
+    }
 }
 
 // wt[ci][tap][co] = w[co][tap][ci] (bf16), the weights of the input-gradient convolution.
@@ -488,42 +503,79 @@ int launch_status(const char* what) {
     return DAS_OK;
 }
 
-// Depth slices per workgroup: 4 when the output has at most 32 channels, 2 up to 64, else 1; channel chunk:
-// the largest of 32, 16, 8 that divides Cin.
-template <int NT, int CC>
-void launch_conv_t(int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride, int in_coff,
-                   const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff, const uint16_t* mk,
-                   int mask_stride, int mask_coff, int cin, int flip, int relu) {
-    constexpr int MT = NT <= 2 ? 4 : (NT <= 4 ? 2 : 1);
+// Workgroup shape: MT depth slices and NT channel tiles (NT divides Cout / 16).  Candidates in order of
+// decreasing work per workgroup; the first with at least 512 workgroups (two per CU) is used, else the one
+// with the most workgroups (small volumes).  The input chunk is the largest of 32, 16, 8 channels dividing Cin.
+template <int MT, int NT, int CC>
+void launch_conv_t(int ngroups, int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride,
+                   int in_coff, const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff,
+                   const uint16_t* mk, int mask_stride, int mask_coff, int cin, int flip, int relu) {
     const unsigned nb = (unsigned)(((vol.W + 7) / 8) * ((vol.H + 7) / 8) * ((vol.D + MT - 1) / MT));
-    hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC>), dim3(nb), dim3(256), 0, s, x, in_stride, in_coff, w, bias,
-                       out, out_stride, out_coff, out_f32, mk, mask_stride, mask_coff, vol, cin, flip, relu);
+    hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC>), dim3(nb, ngroups), dim3(256), 0, s, x, in_stride, in_coff, w,
+                       bias, out, out_stride, out_coff, out_f32, mk, mask_stride, mask_coff, vol, cin, flip, relu);
 }
 
-template <int NT>
-void launch_conv_nt(int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride,
-                    int in_coff, const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff,
-                    const uint16_t* mk, int mask_stride, int mask_coff, int cin, int flip, int relu) {
+template <int MT, int NT>
+void launch_conv_cc(int ngroups, int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x,
+                    int in_stride, int in_coff, const uint16_t* w, const float* bias, void* out, int out_stride,
+                    int out_coff, const uint16_t* mk, int mask_stride, int mask_coff, int cin, int flip, int relu) {
     if (cin % 32 == 0)
-        launch_conv_t<NT, 32>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
-                              mask_stride, mask_coff, cin, flip, relu);
+        launch_conv_t<MT, NT, 32>(ngroups, out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff,
+                                  mk, mask_stride, mask_coff, cin, flip, relu);
     else if (cin % 16 == 0)
-        launch_conv_t<NT, 16>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
-                              mask_stride, mask_coff, cin, flip, relu);
+        launch_conv_t<MT, NT, 16>(ngroups, out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff,
+                                  mk, mask_stride, mask_coff, cin, flip, relu);
     else
-        launch_conv_t<NT, 8>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,
-                             mask_stride, mask_coff, cin, flip, relu);
+        launch_conv_t<MT, NT, 8>(ngroups, out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff,
+                                 mk, mask_stride, mask_coff, cin, flip, relu);
 }
 
-void launch_conv(int nt, int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride,
+struct ConvShape {
+    int mt, nt;
+};
+
+ConvShape pick_conv_shape(int nt_total, const learn::Vol& vol) {
+    // (MT, NT) instantiated below, by decreasing MT * NT
+    static const ConvShape cands[] = {{1, 8}, {1, 7}, {1, 6}, {1, 5}, {2, 4}, {2, 3}, {4, 2}, {4, 1},
+                                      {1, 4}, {1, 3}, {1, 2}, {1, 1}};
+    auto blocks = [&](const ConvShape& c) {
+        return (int64_t)((vol.W + 7) / 8) * ((vol.H + 7) / 8) * ((vol.D + c.mt - 1) / c.mt) * (nt_total / c.nt);
+    };
+    ConvShape best{1, 1};
+    int64_t best_blocks = -1;
+    int best_work = 0;
+    for (const ConvShape& c : cands) {
+        if (nt_total % c.nt) continue;
+        const int64_t b = blocks(c);
+        if (b >= 512 && c.mt * c.nt > best_work) {
+            best = c;
+            best_work = c.mt * c.nt;
+            best_blocks = b;
+        }
+    }
+    if (best_work > 0) return best;
+    for (const ConvShape& c : cands) {
+        if (nt_total % c.nt) continue;
+        if (blocks(c) > best_blocks) {
+            best = c;
+            best_blocks = blocks(c);
+        }
+    }
+    return best;
+}
+
+void launch_conv(int nt_total, int out_f32, const learn::Vol& vol, hipStream_t s, const uint16_t* x, int in_stride,
                  int in_coff, const uint16_t* w, const float* bias, void* out, int out_stride, int out_coff,
                  const uint16_t* mk, int mask_stride, int mask_coff, int cin, int flip, int relu) {
-#define LC(N)                                                                                                     \
-    case N:                                                                                                       \
-        launch_conv_nt<N>(out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,         \
-                          mask_stride, mask_coff, cin, flip, relu);                                               \
-        break;
-    switch (nt) { LC(1) LC(2) LC(3) LC(4) LC(5) LC(6) LC(7) LC(8) }
+    const ConvShape c = pick_conv_shape(nt_total, vol);
+    const int ng = nt_total / c.nt;
+#define LC(M, N)                                                                                                  \
+    if (c.mt == M && c.nt == N) {                                                                                 \
+        launch_conv_cc<M, N>(ng, out_f32, vol, s, x, in_stride, in_coff, w, bias, out, out_stride, out_coff, mk,  \
+                             mask_stride, mask_coff, cin, flip, relu);                                            \
+        return;                                                                                                   \
+    }
+    LC(1, 8) LC(1, 7) LC(1, 6) LC(1, 5) LC(2, 4) LC(2, 3) LC(4, 2) LC(4, 1) LC(1, 4) LC(1, 3) LC(1, 2) LC(1, 1)
 #undef LC
 }
 
@@ -606,9 +658,8 @@ int das_conv3d_wgrad(const void* in, int in_stride, int in_coff, const void* dy,
     launch_wgrad(cout / 16, (cin + 15) / 16, nparts, s, reinterpret_cast<const uint16_t*>(in), in_stride, in_coff,
                  reinterpret_cast<const uint16_t*>(dy), dy_stride, dy_coff, part, part_db, learn::Vol{D, H, W}, cin,
                  cout, chunk);
-    hipLaunchKernelGGL(learn::reduce_parts_kernel, dim3(blocks_for(nw, 256)), dim3(256), 0, s, part, nparts, nw,
-                       dw);
-    hipLaunchKernelGGL(learn::reduce_parts_kernel, dim3(blocks_for(cout, 256)), dim3(256), 0, s, part_db, nparts,
+    hipLaunchKernelGGL(learn::reduce_parts_kernel, dim3(blocks_for(nw, 32)), dim3(256), 0, s, part, nparts, nw, dw);
+    hipLaunchKernelGGL(learn::reduce_parts_kernel, dim3(blocks_for(cout, 32)), dim3(256), 0, s, part_db, nparts,
                        (int64_t)cout, db);
     return launch_status("wgrad launch failed");
 }

@@ -218,7 +218,8 @@ class UNet:
 
     @staticmethod
     def _chunk(v):
-        """Voxels per weight-gradient partial sum: at most 256 partial sums, at least 1024 voxels each."""
+        """Voxels per weight-gradient partial sum: at most 256 partial sums (the weight gradient runs one wave
+        per chunk and tap, so fewer chunks leave CUs idle), at least 1024 voxels each."""
         return max(1024, ((v + 255) // 256 + 31) // 32 * 32)
 
     # -- parameters
