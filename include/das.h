@@ -115,6 +115,18 @@ int das_plan_create(das_plan **out, const das_params *p, const float *elem_xyz,
  * several streams (it is read-only). */
 int das_execute(const das_plan *plan, const void *iq, int dtype, void *out, void *stream);
 
+/* Beamform without compounding: each transmit's volume separately (the
+ * per-plane output layout of the paper's Table 4, i.e. the T = 1 calls of
+ * das_execute in one launch).  The receive geometry of a (voxel, element) pair
+ * is computed once for all transmits.
+ *   iq, dtype, stream  as for das_execute.
+ *   out    device complex64 [T, V, F], 8-byte aligned, fully overwritten.
+ * Supported when T <= 4 and F <= 2 (the plan's kernel then keeps one set of
+ * accumulators per transmit); DAS_ESHAPE otherwise.  Allocates nothing;
+ * asynchronous.  The sum over T equals das_execute's output up to the order
+ * of the float32 additions. */
+int das_execute_per_tx(const das_plan *plan, const void *iq, int dtype, void *out, void *stream);
+
 /* Release a plan and its device memory.  NULL is accepted (no-op).  The
  * caller must ensure no execution using the plan is still in flight. */
 int das_plan_destroy(das_plan *plan);

@@ -23,8 +23,8 @@ DAS_IQ_C16F = 1
 DAS_IQ_C16BF = 2
 
 # Every symbol include/das.h declares.
-EXPORTED = ("das_plan_create", "das_execute", "das_plan_destroy", "das_tx_plane_wave", "das_plan_query",
-            "das_tile_order", "das_status_string", "das_last_error", "das_version")
+EXPORTED = ("das_plan_create", "das_execute", "das_execute_per_tx", "das_plan_destroy", "das_tx_plane_wave",
+            "das_plan_query", "das_tile_order", "das_status_string", "das_last_error", "das_version")
 
 # Every symbol include/das_learn.h declares.
 LEARN_EXPORTED = ("das_conv3d", "das_conv3d_wgrad", "das_conv3d_wgrad_work", "das_transpose_weights",
@@ -67,6 +67,8 @@ def load():
     lib.das_plan_create.restype = ctypes.c_int
     lib.das_execute.argtypes = [vp, vp, ctypes.c_int, vp, vp]
     lib.das_execute.restype = ctypes.c_int
+    lib.das_execute_per_tx.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+    lib.das_execute_per_tx.restype = ctypes.c_int
     lib.das_plan_destroy.argtypes = [vp]
     lib.das_plan_destroy.restype = ctypes.c_int
     lib.das_tx_plane_wave.argtypes = [vp, vp, i64, vp, i32, dbl, vp]

@@ -1,11 +1,11 @@
 """Learned compounding: few-angle delay-and-sum + a 3D U-Net residual.
 
 Compounding N plane waves multiplies the beamforming cost by N.  Here only a
-few of the angles are beamformed (one plan per angle, so each angle's volume
-is kept apart), the network reads their real and imaginary parts (normalised
-by the RMS of their sum) and predicts the residual between the N-angle
-compound and (N / n) times the few-angle sum.  The full N-angle plan stays
-available as the reference and the fallback.
+few of the angles are beamformed (per-transmit output of one plan, so each
+angle's volume is kept apart), the network reads their real and imaginary
+parts (normalised by the RMS of their sum) and predicts the residual between
+the N-angle compound and (N / n) times the few-angle sum.  The full N-angle
+plan stays available as the reference and the fallback.
 
 Argument marshalling only: beamforming, feature packing, the network and the
 output run in the library's kernels (libdas.so).
@@ -71,8 +71,14 @@ class LearnedCompounding:
             raise ValueError("cin must hold 2 channels per input angle")
         self.gain = params.n_tx / self.A
         self.full = _das.Plan(params, elem_xyz, vox_xyz, tx_arrival)
-        one = _das.Params(**{**params.__dict__, "n_tx": 1})
-        self.plans = [_das.Plan(one, elem_xyz, vox_xyz, tx_arrival[t:t + 1].contiguous()) for t in self.input_idx]
+        # the input angles: one plan whose per-transmit output keeps each angle's volume (the receive geometry
+        # is then formed once for all of them), else one plan per angle
+        tx_in = tx_arrival[self.input_idx].contiguous()
+        self.inputs = _das.Plan(_das.Params(**{**params.__dict__, "n_tx": self.A}), elem_xyz, vox_xyz, tx_in)
+        self.per_tx = self.A <= 4 and self.inputs.info()["kernel"][0] <= 2
+        self.plans = [] if self.per_tx else [
+            _das.Plan(_das.Params(**{**params.__dict__, "n_tx": 1}), elem_xyz, vox_xyz, tx_arrival[t:t + 1].contiguous())
+            for t in self.input_idx]
         V = params.n_vox
         dev = vox_xyz.device
         self.V = V
@@ -83,10 +89,17 @@ class LearnedCompounding:
         self.work = torch.zeros(max(1, int(_lib.load().das_compound_work(V))), dtype=torch.float32, device=dev)
         self.net = _learn.UNet(dims, cin=cin, chans=chans, cout=16, device=dev)
 
-    def beamform_inputs(self, iq, stream=None):
-        """The few input angles, one volume each: self.ys [A, V]."""
-        for a, (t, plan) in enumerate(zip(self.input_idx, self.plans)):
-            plan.execute(iq[t:t + 1], out=self.ys[a].view(self.V, 1), stream=stream)
+    def input_iq(self, iq):
+        """The input angles' channel data [A, E, S, 1] out of a full acquisition [T, E, S, 1] (a copy)."""
+        return iq[self.input_idx].contiguous()
+
+    def beamform_inputs(self, iq_in, stream=None):
+        """The input angles (channel data [A, E, S, 1]), one volume each: self.ys [A, V]."""
+        if self.per_tx:
+            self.inputs.execute_per_tx(iq_in, out=self.ys.view(self.A, self.V, 1), stream=stream)
+        else:
+            for a, plan in enumerate(self.plans):
+                plan.execute(iq_in[a:a + 1], out=self.ys[a].view(self.V, 1), stream=stream)
         return self.ys
 
     def features(self, stream=None):
@@ -102,9 +115,10 @@ class LearnedCompounding:
         compound_rescale(y_full, self.scale, out, restore=False, stream=stream)
         return out
 
-    def predict(self, iq, out=None, stream=None):
-        """Few-angle beamforming + network: the estimated compound, complex64 [V, 1]."""
-        self.beamform_inputs(iq, stream)
+    def predict(self, iq_in, out=None, stream=None):
+        """Few-angle beamforming (channel data of the input angles, [A, E, S, 1]) + network: the estimated
+        compound, complex64 [V, 1]."""
+        self.beamform_inputs(iq_in, stream)
         self.features(stream)
         self.net.forward(self.x, stream)
         if out is None:
@@ -114,5 +128,6 @@ class LearnedCompounding:
 
     def close(self):
         self.full.close()
+        self.inputs.close()
         for p in self.plans:
             p.close()

@@ -395,6 +395,7 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
     kp.S = p->n_samples;
     kp.F = p->n_frames;
     kp.n_slots = n_slots;
+    d.n_vox = p->n_vox;
     kp.n_tiles = (int32_t)tl.n_tiles;
     kp.use_apod = p->f_number > 0 ? 1 : 0;
     kp.inv_c = 1.0 / p->sound_speed;
@@ -537,6 +538,24 @@ int das_execute(const das_plan* plan, const void* iq, int dtype, void* out, void
     if (!aligned(out, 8)) return fail(DAS_EALIGN, "out must be 8-byte aligned");
     const hipError_t e = das::launch_das(plan->dev, iq, dtype, out, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e, "launching das kernel");
+    return DAS_OK;
+}
+
+int das_execute_per_tx(const das_plan* plan, const void* iq, int dtype, void* out, void* stream) {
+    g_err.clear();
+    if (!plan_live(plan)) return fail(DAS_EINVAL, "plan is NULL or not live");
+    if (dtype != DAS_IQ_C64 && dtype != DAS_IQ_C16F && dtype != DAS_IQ_C16BF)
+        return fail(DAS_EDTYPE, "unknown IQ dtype %d", dtype);
+    if (plan->p.n_vox > 0 && !das::per_tx_supported(plan->dev))
+        return fail(DAS_ESHAPE, "per-transmit output needs at most 4 transmits and at most 2 frames (plan: T=%d F=%d)",
+                    plan->p.n_tx, plan->p.n_frames);
+    if (plan->p.n_vox == 0) return DAS_OK;
+    if (!iq || !out) return fail(DAS_EINVAL, "iq / out is NULL");
+    const size_t iq_align = dtype == DAS_IQ_C64 ? 8 : 4;
+    if (!aligned(iq, iq_align)) return fail(DAS_EALIGN, "iq must be %zu-byte aligned", iq_align);
+    if (!aligned(out, 8)) return fail(DAS_EALIGN, "out must be 8-byte aligned");
+    const hipError_t e = das::launch_das_per_tx(plan->dev, iq, dtype, out, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "launching per-transmit das kernel");
     return DAS_OK;
 }
 

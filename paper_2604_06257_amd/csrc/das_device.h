@@ -25,6 +25,7 @@ struct das_rx {
 struct das_coef {
     int i0;        // floor(u), valid when active
     int row;       // i0 - first row of the item's window (set by the caller)
+    int t;         // transmit of the item (set by the caller; selects the accumulators in per-transmit output)
     float beta;    // u - floor(u)
     float cr, ci;  // w * exp(+j 2 pi fd tau)
     bool active;   // w > 0 and -1 <= i0 <= S - 1

@@ -44,6 +44,7 @@ struct PlanDev {
     int32_t* item_off = nullptr;  // [n_tiles + 1] offsets into items, in stages
     int32_t* wg_unit = nullptr;   // [n_tiles * chunks] workgroup -> tile * chunks + frame chunk
     int32_t fc = 0, pitch = 0, groups = 1;  // kernel variant: frames per workgroup, LDS row pitch, element groups
+    int64_t n_vox = 0;                      // voxels (per-transmit output stride: n_vox * F)
 };
 
 // Workgroup -> (tile, frame chunk) order: each of the 8 XCDs gets a lateral
@@ -78,6 +79,9 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 hipError_t prepare_variant(const PlanDev& p);
 
 hipError_t launch_das(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s);
+// Per-transmit output [T][V][F] (variants with at most 2 frames per workgroup, T <= 4).
+bool per_tx_supported(const PlanDev& p);
+hipError_t launch_das_per_tx(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s);
 
 hipError_t launch_tx_plane_wave(float* tx_out, const float* vox_xyz, int64_t n_vox, const double* normals_host,
                                 int32_t n_tx, double inv_c, hipStream_t s);

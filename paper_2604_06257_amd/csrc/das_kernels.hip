@@ -171,10 +171,20 @@ constexpr int das_waves_per_simd() {
     return (wgs * G) < 1 ? 1 : ((wgs * G) > cap ? cap : wgs * G);
 }
 
-template <int FC, int P, int DT, int G>
-__global__ __launch_bounds__(kSlots* G) __attribute__((amdgpu_waves_per_eu(das_waves_per_simd<FC, P, G>(), das_waves_per_simd<FC, P, G>())))
-void das_kernel(PlanDev p, const void* __restrict__ iq,
-                                                       float2* __restrict__ out, int vec) {
+// NTX > 1: per-transmit output.  Each lane keeps NTX sets of FC accumulators and adds an item into the set of
+// its transmit (wave-uniform, so the choice is a scalar branch); out is [T][V][F] (tx_stride = V * F).  Only
+// for single-group variants with at most 2 frames per workgroup (registers), and T <= NTX.
+template <int FC, int P, int G, int NTX>
+constexpr int das_waves_ntx() {
+    constexpr int w = das_waves_per_simd<FC, P, G>();
+    return (NTX > 1 && FC > 1 && w > 6) ? 6 : w;  // per-transmit accumulators of 2 frames: 80 VGPRs
+}
+
+template <int FC, int P, int DT, int G, int NTX = 1>
+__global__ __launch_bounds__(kSlots* G) __attribute__((amdgpu_waves_per_eu(das_waves_ntx<FC, P, G, NTX>(),
+                                                                            das_waves_ntx<FC, P, G, NTX>())))
+void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out, int vec, int64_t tx_stride) {
+    static_assert(NTX == 1 || (G == 1 && FC <= 2 && !stage_pairs(FC)), "per-transmit output: G = 1, FC <= 2");
     constexpr int kRows = P - 1;
     constexpr int kBuf = FC * P;  // float4 per buffer
     constexpr int kEB = IQType<DT>::kBytes;
@@ -201,9 +211,9 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
     const int fbase = f0 + fgrp * FPT;
     const bool full_frames = vec && (fbase + FPT <= kp.F);
 
-    float acc_r[FC], acc_i[FC];
+    float acc_r[NTX * FC], acc_i[NTX * FC];
 #pragma unroll
-    for (int f = 0; f < FC; ++f) {
+    for (int f = 0; f < NTX * FC; ++f) {
         acc_r[f] = 0.0f;
         acc_i[f] = 0.0f;
     }
@@ -303,22 +313,33 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
         das_coef c = das_tx_setup(rx, txv, kp);
         const bool use = live && (vox >= 0) && c.active && c.i0 >= it.z && c.i0 < it.z + it.w;
         c.row = use ? c.i0 - it.z + base : 0;
+        c.t = it.x;
         c.beta = use ? c.beta : 0.0f;
         c.cr = use ? c.cr : 0.0f;
         c.ci = use ? c.ci : 0.0f;
         return c;
     };
-    auto mac_item = [&](const das_coef& c, const float4* buf) {
+    auto mac_into = [&](const das_coef& c, const float4* buf, int a0) {
         const float4* src = buf + c.row;
 #pragma unroll
         for (int f = 0; f < FC; ++f) {
             const float4 d = src[((f % FPT) * NFG + f / FPT) * P];
             const float tr = fmaf(c.beta, d.z, d.x);
             const float ti = fmaf(c.beta, d.w, d.y);
-            acc_r[f] = fmaf(c.cr, tr, acc_r[f]);
-            acc_r[f] = fmaf(-c.ci, ti, acc_r[f]);
-            acc_i[f] = fmaf(c.cr, ti, acc_i[f]);
-            acc_i[f] = fmaf(c.ci, tr, acc_i[f]);
+            acc_r[a0 + f] = fmaf(c.cr, tr, acc_r[a0 + f]);
+            acc_r[a0 + f] = fmaf(-c.ci, ti, acc_r[a0 + f]);
+            acc_i[a0 + f] = fmaf(c.cr, ti, acc_i[a0 + f]);
+            acc_i[a0 + f] = fmaf(c.ci, tr, acc_i[a0 + f]);
+        }
+    };
+    auto mac_item = [&](const das_coef& c, const float4* buf) {
+        if constexpr (NTX == 1) {
+            mac_into(c, buf, 0);
+        } else {
+            const int t = __builtin_amdgcn_readfirstlane(c.t);
+#pragma unroll
+            for (int j = 0; j < NTX; ++j)
+                if (t == j) mac_into(c, buf, j * FC);
         }
     };
 
@@ -399,10 +420,14 @@ void das_kernel(PlanDev p, const void* __restrict__ iq,
         }
     }
     if (grp == 0 && vox >= 0) {
-        float2* o = out + (size_t)vox * kp.F;
 #pragma unroll
-        for (int f = 0; f < FC; ++f)
-            if (f0 + f < kp.F) o[f0 + f] = make_float2(acc_r[f], acc_i[f]);
+        for (int j = 0; j < NTX; ++j) {
+            if (NTX > 1 && j >= kp.T) break;
+            float2* o = out + j * tx_stride + (size_t)vox * kp.F;
+#pragma unroll
+            for (int f = 0; f < FC; ++f)
+                if (f0 + f < kp.F) o[f0 + f] = make_float2(acc_r[j * FC + f], acc_i[j * FC + f]);
+        }
     }
 }
 
@@ -421,41 +446,63 @@ static int vec_loads_ok(const PlanDev& p, const void* iq) {
     return (p.kp.F % FPT == 0) && (reinterpret_cast<uintptr_t>(iq) % (FPT * kEB) == 0);
 }
 
-template <int FC, int P, int G>
+template <int FC, int P, int G, int NTX = 1>
 static hipError_t launch_v(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
     const dim3 grid((unsigned)(p.kp.n_tiles * ((p.kp.F + FC - 1) / FC)));
     const dim3 block(kSlots * G);
     const size_t sh = lds_bytes<FC, P, G>();
     float2* o = reinterpret_cast<float2*>(out);
+    const int64_t txs = (int64_t)p.n_vox * p.kp.F;
     switch (dtype) {
         case DAS_IQ_C64:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C64, G>), grid, block, sh, s, p, iq, o,
-                               vec_loads_ok<FC, DAS_IQ_C64>(p, iq));
+            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C64, G, NTX>), grid, block, sh, s, p, iq, o,
+                               vec_loads_ok<FC, DAS_IQ_C64>(p, iq), txs);
             break;
         case DAS_IQ_C16F:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16F, G>), grid, block, sh, s, p, iq, o,
-                               vec_loads_ok<FC, DAS_IQ_C16F>(p, iq));
+            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16F, G, NTX>), grid, block, sh, s, p, iq, o,
+                               vec_loads_ok<FC, DAS_IQ_C16F>(p, iq), txs);
             break;
         default:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16BF, G>), grid, block, sh, s, p, iq, o,
-                               vec_loads_ok<FC, DAS_IQ_C16BF>(p, iq));
+            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16BF, G, NTX>), grid, block, sh, s, p, iq, o,
+                               vec_loads_ok<FC, DAS_IQ_C16BF>(p, iq), txs);
             break;
     }
     return hipGetLastError();
 }
 
-template <int FC, int P, int G>
-static hipError_t set_lds_limit() {
+template <int FC, int P, int G, int NTX = 1>
+static hipError_t set_lds_limit_ntx() {
     const int sh = (int)lds_bytes<FC, P, G>();
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C64, G>,
+    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C64, G, NTX>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
         return e;
-    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16F, G>,
+    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16F, G, NTX>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
         return e;
-    return hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16BF, G>,
+    return hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16BF, G, NTX>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, sh);
+}
+
+// Per-transmit output exists for the variants with at most 2 frames per workgroup (all single-group).
+constexpr int kPerTx = 4;
+template <int FC, int P, int G>
+static constexpr bool has_per_tx() {
+    return G == 1 && FC <= 2;
+}
+
+template <int FC, int P, int G>
+static hipError_t set_lds_limit() {
+    hipError_t e = set_lds_limit_ntx<FC, P, G, 1>();
+    if (e != hipSuccess) return e;
+    if constexpr (has_per_tx<FC, P, G>()) return set_lds_limit_ntx<FC, P, G, kPerTx>();
+    return hipSuccess;
+}
+
+template <int FC, int P, int G>
+static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
+    if constexpr (has_per_tx<FC, P, G>()) return launch_v<FC, P, G, kPerTx>(p, iq, dtype, out, s);
+    return hipErrorInvalidValue;
 }
 
 // Variants: FC = frames per workgroup (power of two), P = row pitch, G = groups.
@@ -514,6 +561,17 @@ hipError_t launch_das(const PlanDev& p, const void* iq, int dtype, void* out, hi
     if (p.fc == FC_ && p.pitch == P_ && p.groups == G_) return launch_v<FC_, P_, G_>(p, iq, dtype, out, s);
     DAS_VARIANTS(DAS_LAUNCH)
 #undef DAS_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+bool per_tx_supported(const PlanDev& p) { return p.groups == 1 && p.fc <= 2 && p.kp.T <= kPerTx; }
+
+hipError_t launch_das_per_tx(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
+    if (p.kp.n_tiles == 0) return hipSuccess;
+#define DAS_LAUNCH_TX(FC_, P_, G_) \
+    if (p.fc == FC_ && p.pitch == P_ && p.groups == G_) return launch_per_tx_v<FC_, P_, G_>(p, iq, dtype, out, s);
+    DAS_VARIANTS(DAS_LAUNCH_TX)
+#undef DAS_LAUNCH_TX
     return hipErrorInvalidValue;
 }
 

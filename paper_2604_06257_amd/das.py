@@ -111,6 +111,22 @@ class Plan:
                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def execute_per_tx(self, iq, out=None, stream=None):
+        """Each transmit's volume separately (das_execute_per_tx): complex64 [T, V, F]; T <= 4, F <= 2."""
+        p = self.params
+        code = iq_dtype_code(iq)
+        want = (p.n_tx, p.n_elem, p.n_samples, p.n_frames) + (() if code == _lib.DAS_IQ_C64 else (2,))
+        if not iq.is_cuda or tuple(iq.shape) != want or not iq.is_contiguous():
+            raise ValueError("iq must be a contiguous CUDA tensor of shape %s, got %s" % (want, tuple(iq.shape)))
+        shape = (p.n_tx, p.n_vox, p.n_frames)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex64, device=iq.device)
+        elif out.dtype != torch.complex64 or tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError("out must be contiguous complex64 of shape %s" % (shape,))
+        check(_lib.load().das_execute_per_tx(self._h, ctypes.c_void_p(iq.data_ptr()), code,
+                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             check(_lib.load().das_plan_destroy(self._h))

@@ -10,7 +10,8 @@ input-angle sum.  Everything stays in device memory.  Training is Adam on one
 volume per step; the validation set picks the checkpoint; evaluation reports the normalised RMS error in dB against
 the full compound for the scaled few-angle sum (no network) and for the
 network, and the speedup t(full) / (t(input angles) + t(features) +
-t(network) + t(output)).
+t(network) + t(output)); the input angles are beamformed from their own
+channel data, [A, E, S, 1], as an acquisition of only those angles records it.
 
 ``--geometry small`` is a reduced case (8 x 8 array, 32^3 grid, 512 samples)
 for quick runs.
@@ -85,7 +86,7 @@ class Dataset:
             echo_iq_gpu(geo["elem"], geo["angles"], scat, amp, n_samples=p["n_samples"], n_frames=1, c=p["c"],
                         fs=p["fs"], fc=p["fc"], fd=p["fd"], t0=p["t0"], out=iq, device=dev)
             lc.full_compound(iq, out=y_full)
-            lc.beamform_inputs(iq)
+            lc.beamform_inputs(lc.input_iq(iq))
             lc.features()
             self.x[i].copy_(lc.x)
             self.base[i].copy_(lc.base)
@@ -127,13 +128,14 @@ def time_paths(lc, geo, reps=5):
     scat, amp = geo["phantom"](10 ** 6)
     iq = echo_iq_gpu(geo["elem"], geo["angles"], scat, amp, n_samples=p["n_samples"], n_frames=1, c=p["c"],
                      fs=p["fs"], fc=p["fc"], fd=p["fd"], t0=p["t0"], device=dev)
+    iq_in = lc.input_iq(iq)  # what an acquisition of only the input angles records
     y = torch.empty((lc.V, 1), dtype=torch.complex64, device=dev)
     out = torch.empty((lc.V, 1), dtype=torch.complex64, device=dev)
     stages = {"full_das": lambda: lc.full_compound(iq, out=y),
-              "input_das": lambda: lc.beamform_inputs(iq),
+              "input_das": lambda: lc.beamform_inputs(iq_in),
               "features": lambda: lc.features(),
               "network": lambda: lc.net.forward(lc.x),
-              "learned_total": lambda: lc.predict(iq, out=out)}
+              "learned_total": lambda: lc.predict(iq_in, out=out)}
     res = {}
     for name, fn in stages.items():
         fn()

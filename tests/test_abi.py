@@ -84,6 +84,8 @@ def test_plan_create_rejects_null_and_misaligned():
 def test_execute_and_query_reject_dead_plans():
     lib = _lib.load()
     assert lib.das_execute(None, FAKE, 0, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_execute_per_tx(None, FAKE, 0, FAKE, None) == _lib.DAS_EINVAL
+    assert lib.das_execute_per_tx(ctypes.c_void_p(0x4000), FAKE, 0, FAKE, None) == _lib.DAS_EINVAL
     assert lib.das_execute(ctypes.c_void_p(0x4000), FAKE, 0, FAKE, None) == _lib.DAS_EINVAL  # never created
     info = _lib.DasPlanInfo()
     assert lib.das_plan_query(None, ctypes.byref(info)) == _lib.DAS_EINVAL

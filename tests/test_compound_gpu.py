@@ -85,9 +85,12 @@ def test_full_compound_is_the_sum_of_single_angle_volumes():
         with das.Plan(one, elem, vox, tx[t:t + 1].contiguous()) as plan:
             acc += plan.execute(iq[t:t + 1]).cpu().numpy()[:, 0]
     assert np.linalg.norm(full - acc) <= 1e-5 * np.linalg.norm(full)
-    # the input-angle volumes are the same one-angle plans
-    ys = lc.beamform_inputs(iq).cpu().numpy()
-    assert np.abs(ys).max() > 0
+    # the input-angle volumes (per-transmit output of one plan) are the one-angle plans' volumes
+    assert lc.per_tx
+    ys = lc.beamform_inputs(lc.input_iq(iq)).cpu().numpy()
+    for a, t in enumerate(lc.input_idx):
+        with das.Plan(one, elem, vox, tx[t:t + 1].contiguous()) as plan:
+            np.testing.assert_array_equal(ys[a], plan.execute(iq[t:t + 1]).cpu().numpy()[:, 0])
     lc.close()
 
 
