@@ -323,3 +323,17 @@ def test_per_transmit_output_rejects_unsupported_plans():
     with das.Plan(params, dev(elem), dev(vox), dev(tx)) as plan:
         with pytest.raises(ValueError):
             plan.execute_per_tx(dev(iq))
+
+
+@pytest.mark.parametrize("kind,F", [("f16", 32), ("bf16", 16), ("c64", 24)])
+def test_paired_stages_parity(kind, F):
+    """Variants with 16 frames per workgroup stage two element windows per step: parity against the oracle on
+    the same (quantised) samples, for each IQ type (their fill threads cover different row counts)."""
+    iq, elem, vox, tx, p = small_case(900 + F, T=2, E=24, S=96, F=F, V=600, depth=(0.3e-3, 2.0e-3))
+    y, info, iq_t = gpu_das(iq, elem, vox, tx, p, iq_dtype=kind)
+    assert info["kernel"][0] == 16
+    iq_q = iq if kind == "c64" else iq_t.float().cpu().numpy().view(np.complex64)[..., 0]
+    ref = oracle.das(iq_q, elem, vox, tx, **p)
+    db = oracle.nrmse_db(y, ref)
+    print(kind, F, "nrmse dB", db, info)
+    assert db <= DB_BAR
