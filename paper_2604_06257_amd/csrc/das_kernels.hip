@@ -173,7 +173,7 @@ constexpr int das_waves_per_simd() {
 
 // NTX > 1: per-transmit output.  Each lane keeps NTX sets of FC accumulators and adds an item into the set of
 // its transmit (wave-uniform, so the choice is a scalar branch); out is [T][V][F] (tx_stride = V * F).  Only
-// for single-group variants with at most 2 frames per workgroup (registers), and T <= NTX.
+// for variants with at most 2 frames per workgroup (registers), and T <= NTX.
 template <int FC, int P, int G, int NTX>
 constexpr int das_waves_ntx() {
     constexpr int w = das_waves_per_simd<FC, P, G>();
@@ -184,7 +184,7 @@ template <int FC, int P, int DT, int G, int NTX = 1>
 __global__ __launch_bounds__(kSlots* G) __attribute__((amdgpu_waves_per_eu(das_waves_ntx<FC, P, G, NTX>(),
                                                                             das_waves_ntx<FC, P, G, NTX>())))
 void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out, int vec, int64_t tx_stride) {
-    static_assert(NTX == 1 || (G == 1 && FC <= 2 && !stage_pairs(FC)), "per-transmit output: G = 1, FC <= 2");
+    static_assert(NTX == 1 || (FC <= 2 && !stage_pairs(FC)), "per-transmit output: FC <= 2");
     constexpr int kRows = P - 1;
     constexpr int kBuf = FC * P;  // float4 per buffer
     constexpr int kEB = IQType<DT>::kBytes;
@@ -401,17 +401,17 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     if (G > 1) {
         // Fixed-order reduction of the groups' partial sums through LDS:
         // ((g0 + g1) + g2) + ...
-        float2* red = reinterpret_cast<float2*>(lds);  // [FC][kSlots]
+        float2* red = reinterpret_cast<float2*>(lds);  // [NTX * FC][kSlots]
         for (int g = 1; g < G; ++g) {
             __syncthreads();
             if (grp == g) {
 #pragma unroll
-                for (int f = 0; f < FC; ++f) red[f * kSlots + gt] = make_float2(acc_r[f], acc_i[f]);
+                for (int f = 0; f < NTX * FC; ++f) red[f * kSlots + gt] = make_float2(acc_r[f], acc_i[f]);
             }
             __syncthreads();
             if (grp == 0) {
 #pragma unroll
-                for (int f = 0; f < FC; ++f) {
+                for (int f = 0; f < NTX * FC; ++f) {
                     const float2 v = red[f * kSlots + gt];
                     acc_r[f] += v.x;
                     acc_i[f] += v.y;
@@ -431,10 +431,10 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     }
 }
 
-template <int FC, int P, int G>
+template <int FC, int P, int G, int NTX = 1>
 static size_t lds_bytes() {
     const size_t win = (size_t)G * 2 * FC * P * sizeof(float4);
-    const size_t red = (size_t)(G > 1 ? 1 : 0) * FC * kSlots * sizeof(float2);
+    const size_t red = (size_t)(G > 1 ? 1 : 0) * NTX * FC * kSlots * sizeof(float2);
     return win > red ? win : red;
 }
 
@@ -450,7 +450,7 @@ template <int FC, int P, int G, int NTX = 1>
 static hipError_t launch_v(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
     const dim3 grid((unsigned)(p.kp.n_tiles * ((p.kp.F + FC - 1) / FC)));
     const dim3 block(kSlots * G);
-    const size_t sh = lds_bytes<FC, P, G>();
+    const size_t sh = lds_bytes<FC, P, G, NTX>();
     float2* o = reinterpret_cast<float2*>(out);
     const int64_t txs = (int64_t)p.n_vox * p.kp.F;
     switch (dtype) {
@@ -472,7 +472,7 @@ static hipError_t launch_v(const PlanDev& p, const void* iq, int dtype, void* ou
 
 template <int FC, int P, int G, int NTX = 1>
 static hipError_t set_lds_limit_ntx() {
-    const int sh = (int)lds_bytes<FC, P, G>();
+    const int sh = (int)lds_bytes<FC, P, G, NTX>();
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C64, G, NTX>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
@@ -484,11 +484,11 @@ static hipError_t set_lds_limit_ntx() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, sh);
 }
 
-// Per-transmit output exists for the variants with at most 2 frames per workgroup (all single-group).
+// Per-transmit output exists for the variants with at most 2 frames per workgroup.
 constexpr int kPerTx = 4;
 template <int FC, int P, int G>
 static constexpr bool has_per_tx() {
-    return G == 1 && FC <= 2;
+    return FC <= 2;
 }
 
 template <int FC, int P, int G>
@@ -511,7 +511,8 @@ static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, v
 #define DAS_VARIANTS(X)                                                                              \
     X(32, 41, 3) X(32, 49, 3) X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
     X(8, 129, 1) X(8, 257, 1) X(4, 33, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
-    X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 65, 1) X(1, 129, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1)
+    X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 65, 1) X(1, 129, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1) \
+    X(1, 65, 4) X(1, 129, 4) X(1, 257, 4) X(2, 129, 4) X(2, 257, 4) X(4, 65, 4) X(4, 129, 4)
 
 // Variant choice (measured on MI355X with the c1 / c2 / c3 workloads):
 //  - frames are cut into chunks of FC; more chunks mean more workgroups, which
@@ -519,7 +520,8 @@ static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, v
 //    coefficients once per chunk;
 //  - the LDS pitch is the smallest that holds the largest tile window in one
 //    piece (a split window costs a whole extra multiply-accumulate pass);
-//  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks.
+//  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks;
+//  - with up to 4 frames and fewer than two workgroups per CU, four element groups share each tile.
 Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
     int fc;
     if (frames >= 32) fc = (n_tiles < 512) ? 16 : 32;
@@ -544,6 +546,13 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
     }
     DAS_VARIANTS(DAS_PICK)
 #undef DAS_PICK
+    // up to 4 frames and fewer than two workgroups per CU: four element groups per tile (16 waves) for occupancy
+    if (best.fc <= 4 && n_tiles * ((frames + best.fc - 1) / best.fc) < 512) {
+#define DAS_G4(FC_, P_, G_) \
+    if (FC_ == best.fc && G_ == 4 && P_ == best.pitch) return Variant{FC_, P_, G_};
+        DAS_VARIANTS(DAS_G4)
+#undef DAS_G4
+    }
     return best;
 }
 
@@ -564,7 +573,7 @@ hipError_t launch_das(const PlanDev& p, const void* iq, int dtype, void* out, hi
     return hipErrorInvalidValue;
 }
 
-bool per_tx_supported(const PlanDev& p) { return p.groups == 1 && p.fc <= 2 && p.kp.T <= kPerTx; }
+bool per_tx_supported(const PlanDev& p) { return p.fc <= 2 && p.kp.T <= kPerTx; }
 
 hipError_t launch_das_per_tx(const PlanDev& p, const void* iq, int dtype, void* out, hipStream_t s) {
     if (p.kp.n_tiles == 0) return hipSuccess;
