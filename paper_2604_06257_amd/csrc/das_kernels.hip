@@ -512,46 +512,71 @@ static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, v
     X(32, 41, 3) X(32, 49, 3) X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
     X(8, 129, 1) X(8, 257, 1) X(4, 33, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
     X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 65, 1) X(1, 129, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1) \
-    X(1, 65, 4) X(1, 129, 4) X(1, 257, 4) X(2, 129, 4) X(2, 257, 4) X(4, 65, 4) X(4, 129, 4)
+    X(1, 65, 4) X(1, 129, 4) X(1, 257, 4) X(2, 129, 4) X(2, 257, 4) X(4, 65, 4) X(4, 129, 4) X(8, 65, 2) X(8, 65, 4) X(8, 33, 2) X(8, 129, 2) X(16, 65, 4) X(4, 65, 2) \
+    X(1, 65, 2) X(1, 129, 2) X(1, 257, 2) X(2, 129, 2) X(2, 257, 2) X(4, 129, 2) X(8, 129, 4)
 
-// Variant choice (measured on MI355X with the c1 / c2 / c3 workloads):
+// Variant choice (measured on MI355X with the c1 / c2 / c3 workloads and sweeps of grid size (64-1024 tiles),
+// frame count (1-24) and element count (64-256) around the c2 geometry):
 //  - frames are cut into chunks of FC; more chunks mean more workgroups, which
 //    the heaviest-first dispatch order balances, at the cost of forming the
 //    coefficients once per chunk;
 //  - the LDS pitch is the smallest that holds the largest tile window in one
-//    piece (a split window costs a whole extra multiply-accumulate pass);
-//  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks;
-//  - with up to 4 frames and fewer than two workgroups per CU, four element groups share each tile.
+//    piece (a split window costs a whole extra multiply-accumulate pass), and at least 65 rows for
+//    8- and 16-frame chunks (33-row variants measured 5-17% slower there);
+//  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks; 5-8 frames take 8-frame chunks
+//    unless the grid is large (then 4-frame chunks, which hold 8 waves per SIMD);
+//  - with fewer workgroups than CUs (256), the frame chunk is halved until there are enough;
+//  - a launch should then hold about 6144 waves (FC <= 4) or 2560 waves (FC >= 8): element groups
+//    (4 waves each) are added until it does, up to 4 groups (16 waves per workgroup).
+static bool variant_exists(int fc, int pitch, int g) {
+#define DAS_HAS(FC_, P_, G_) \
+    if (FC_ == fc && P_ == pitch && G_ == g) return true;
+    DAS_VARIANTS(DAS_HAS)
+#undef DAS_HAS
+    return false;
+}
+
+// smallest pitch >= min_pitch with a (fc, pitch, g) variant, or 0
+static int pitch_at_least(int fc, int min_pitch, int g) {
+    int best = 0;
+#define DAS_PIT(FC_, P_, G_) \
+    if (FC_ == fc && G_ == g && P_ >= min_pitch && (best == 0 || P_ < best)) best = P_;
+    DAS_VARIANTS(DAS_PIT)
+#undef DAS_PIT
+    return best;
+}
+
 Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
     int fc;
     if (frames >= 32) fc = (n_tiles < 512) ? 16 : 32;
     else if (frames > 8) fc = 16;
-    else if (frames > 4) fc = 4;
+    else if (frames > 4) fc = (n_tiles <= 2048) ? 8 : 4;
     else fc = frames > 2 ? 4 : frames > 1 ? 2 : 1;
     if (const char* env = std::getenv("DAS_VARIANT")) {  // tuning override: "fc,pitch,groups"
         int f = 0, pp = 0, g = 0;
-        if (std::sscanf(env, "%d,%d,%d", &f, &pp, &g) == 3 && f <= (frames >= 32 ? 32 : fc * 2)) {
-#define DAS_FIND(FC_, P_, G_) \
-    if (FC_ == f && P_ == pp && G_ == g) return Variant{FC_, P_, G_};
-            DAS_VARIANTS(DAS_FIND)
-#undef DAS_FIND
-        }
+        if (std::sscanf(env, "%d,%d,%d", &f, &pp, &g) == 3 && f <= (frames >= 32 ? 32 : fc * 2) &&
+            variant_exists(f, pp, g))
+            return Variant{f, pp, g};
     }
     if (fc == 32 && max_window <= 40) return Variant{32, 41, 3};
     if (fc == 32 && max_window <= 48) return Variant{32, 49, 3};
+    auto chunks = [&](int f) { return (int64_t)((frames + f - 1) / f); };
+    if (fc <= 16)
+        while (fc > 1 && n_tiles * chunks(fc) < 256) fc /= 2;
+    const int base_g = fc >= 16 ? 2 : 1;
+    const int min_pitch = fc >= 8 ? 65 : 0;
     Variant best{0, 0, 0};
-#define DAS_PICK(FC_, P_, G_)                                                                  \
-    if (FC_ == fc && (G_ <= 2)) {                                                              \
+#define DAS_PICK(FC_, P_, G_)                                                                       \
+    if (FC_ == fc && G_ == base_g && P_ >= min_pitch) {                                             \
         if (best.fc == 0 || (best.pitch - 1 < max_window && P_ > best.pitch)) best = {FC_, P_, G_}; \
     }
     DAS_VARIANTS(DAS_PICK)
 #undef DAS_PICK
-    // up to 4 frames and fewer than two workgroups per CU: four element groups per tile (16 waves) for occupancy
-    if (best.fc <= 4 && n_tiles * ((frames + best.fc - 1) / best.fc) < 512) {
-#define DAS_G4(FC_, P_, G_) \
-    if (FC_ == best.fc && G_ == 4 && P_ == best.pitch) return Variant{FC_, P_, G_};
-        DAS_VARIANTS(DAS_G4)
-#undef DAS_G4
+    if (best.fc == 0 || best.fc > 16) return best;
+    const int64_t target = best.fc <= 4 ? 6144 : 2560;
+    for (int g = base_g; g <= 4; g *= 2) {
+        const int p = pitch_at_least(best.fc, best.pitch, g);
+        if (p != 0 && (n_tiles * chunks(best.fc) * 4 * g >= target || g == 4)) return Variant{best.fc, p, g};
     }
     return best;
 }
