@@ -188,8 +188,25 @@ const char *das_status_string(int status);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *das_last_error(void);
 
-/* ABI version: (major << 16) | minor (this header: 1.1). */
+/* ABI version: (major << 16) | minor (this header: 1.2). */
 int das_version(void);
+
+/* The compiled beamforming kernel variants, as (frames per workgroup, LDS row
+ * pitch, element groups) triples; das_plan_info reports which one a plan uses.
+ *   fc_pitch_groups  host int32 [3 * capacity] or NULL: receives the first
+ *                    min(count, capacity) triples.
+ *   capacity         >= 0 (0 with NULL asks for the count only).
+ * Returns the number of variants (> 0), or a negative status (DAS_EINVAL).
+ * Host-only; no GPU call.
+ *
+ * das_plan_create picks the variant from the frame count, the largest tile
+ * window and the tile count.  For tuning and tests, the environment variable
+ * DAS_VARIANT="fc,pitch,groups", read at plan creation, forces a listed
+ * variant when fc is at most twice the frames per workgroup the plan would
+ * choose (any fc up to 32 when F >= 32); otherwise it is ignored.  Every
+ * variant computes the same sums (element groups fold their partial sums in
+ * a different order, so results may differ in the last bits). */
+int das_kernel_variants(int32_t *fc_pitch_groups, int32_t capacity);
 
 #ifdef __cplusplus
 }

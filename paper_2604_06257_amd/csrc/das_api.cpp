@@ -310,7 +310,14 @@ static hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 extern "C" {
 
-int das_version(void) { return (1 << 16) | 1; }
+int das_version(void) { return (1 << 16) | 2; }
+
+int das_kernel_variants(int32_t* fc_pitch_groups, int32_t capacity) {
+    g_err.clear();
+    if (capacity < 0) return fail(DAS_EINVAL, "capacity < 0");
+    if (capacity > 0 && !fc_pitch_groups) return fail(DAS_EINVAL, "fc_pitch_groups is NULL");
+    return das::list_variants(fc_pitch_groups, capacity);
+}
 
 const char* das_last_error(void) { return g_err.c_str(); }
 

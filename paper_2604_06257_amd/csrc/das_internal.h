@@ -58,6 +58,10 @@ struct Variant {
 };
 Variant choose_variant(int frames, int max_window, int64_t n_tiles);
 
+// The compiled variants as (fc, pitch, groups) triples: writes min(count, capacity) of them to out (when not
+// null) and returns the count.
+int list_variants(int32_t* out, int capacity);
+
 // Whether a variant stages two items per step (the plan packs stages only for such variants): with 8 or
 // more frames per workgroup the saved fill and barrier outweigh the extra registers.
 constexpr bool stage_pairs(int fc) { return fc >= 8; }

@@ -581,6 +581,22 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
     return best;
 }
 
+int list_variants(int32_t* out, int capacity) {
+    int n = 0;
+#define DAS_LIST(FC_, P_, G_)                 \
+    {                                         \
+        if (out != nullptr && n < capacity) { \
+            out[3 * n] = FC_;                 \
+            out[3 * n + 1] = P_;              \
+            out[3 * n + 2] = G_;              \
+        }                                     \
+        ++n;                                  \
+    }
+    DAS_VARIANTS(DAS_LIST)
+#undef DAS_LIST
+    return n;
+}
+
 hipError_t prepare_variant(const PlanDev& p) {
 #define DAS_LIMIT(FC_, P_, G_) \
     if (p.fc == FC_ && p.pitch == P_ && p.groups == G_) return set_lds_limit<FC_, P_, G_>();

@@ -170,6 +170,19 @@ def tile_order(vox_xyz):
     return out, tuple(dims)
 
 
+def kernel_variants():
+    """The compiled kernel variants (das_kernel_variants): list of (fc, pitch, groups)."""
+    lib = _lib.load()
+    n = lib.das_kernel_variants(None, 0)
+    if n < 0:
+        check(n)
+    buf = (ctypes.c_int32 * (3 * n))()
+    n2 = lib.das_kernel_variants(buf, n)
+    if n2 < 0:
+        check(n2)
+    return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(n)]
+
+
 def beamform(iq, elem_xyz, vox_xyz, tx_arrival, params, out=None, stream=None):
     """One-shot convenience: plan, execute, destroy."""
     with Plan(params, elem_xyz, vox_xyz, tx_arrival, stream=stream) as plan:

@@ -34,6 +34,25 @@ def test_library_exports_every_declared_symbol():
     assert lib.das_version() >> 16 == 1
 
 
+def test_kernel_variants_list():
+    """das_kernel_variants (host-only): a non-empty list of distinct, well-formed variants; the count-only call,
+    a short buffer and argument errors behave as documented."""
+    lib = _lib.load()
+    n = lib.das_kernel_variants(None, 0)
+    assert n > 0
+    vs = das.kernel_variants()
+    assert len(vs) == n and len(set(vs)) == n
+    for fc, pitch, groups in vs:
+        assert fc in (1, 2, 4, 8, 16, 32)
+        assert pitch % 2 == 1 and fc * (pitch - 1) <= 2048  # odd pitch; prefetch and LDS offset bounds
+        assert groups in (1, 2, 3, 4)
+    short = (ctypes.c_int32 * 3)()
+    assert lib.das_kernel_variants(short, 1) == n
+    assert tuple(short) == vs[0]
+    assert lib.das_kernel_variants(None, 5) == _lib.DAS_EINVAL
+    assert lib.das_kernel_variants(short, -1) == _lib.DAS_EINVAL
+
+
 def test_status_strings():
     lib = _lib.load()
     assert lib.das_status_string(0) == b"ok"

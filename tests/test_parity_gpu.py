@@ -346,3 +346,39 @@ def test_paired_stages_parity(kind, F, monkeypatch):
     db = oracle.nrmse_db(y, ref)
     print(kind, F, "nrmse dB", db, info)
     assert db <= DB_BAR
+
+
+_VARIANT_REFS = {}
+
+
+@pytest.mark.parametrize("kind", ["c64", "f16", "bf16"])
+def test_every_kernel_variant(kind, monkeypatch):
+    """Every compiled variant (forced through DAS_VARIANT), for each IQ type: parity with the FP64 oracle on the
+    same (quantised) samples, with a ragged last frame chunk (F = FC + FC / 2) and two transmits."""
+    failures = []
+    for fc, pitch, groups in das.kernel_variants():
+        F = fc + max(1, fc // 2)
+        key = (F, kind)
+        if key not in _VARIANT_REFS:
+            iq, elem, vox, tx, p = small_case(1200 + F, T=2, E=24, S=96, F=F, V=600, depth=(0.3e-3, 2.0e-3))
+            iq_t = None
+            if kind != "c64":
+                dt = torch.float16 if kind == "f16" else torch.bfloat16
+                iq_t = torch.view_as_real(torch.from_numpy(iq.astype(np.complex64))).to(dt).contiguous()
+                iq_q = iq_t.float().numpy().view(np.complex64)[..., 0]
+            else:
+                iq_q = iq
+            _VARIANT_REFS[key] = (iq_q, iq_t, elem, vox, tx, p, oracle.das(iq_q, elem, vox, tx, **p))
+        iq_q, iq_t, elem, vox, tx, p, ref = _VARIANT_REFS[key]
+        monkeypatch.setenv("DAS_VARIANT", "%d,%d,%d" % (fc, pitch, groups))
+        params = das.Params(n_tx=2, n_elem=24, n_samples=96, n_frames=F, n_vox=vox.shape[0], sound_speed=p["c"],
+                            fs=p["fs"], f_demod=p["fd"], t0=p["t0"], f_number=p["f_number"],
+                            tukey_alpha=p["tukey_alpha"])
+        with das.Plan(params, dev(elem), dev(vox), dev(tx)) as plan:
+            got = plan.info()["kernel"]
+            x = dev(iq_q.astype(np.complex64)) if kind == "c64" else iq_t.cuda()
+            y = plan.execute(x).cpu().numpy()
+        db = oracle.nrmse_db(y, ref)
+        if got != (fc, pitch, groups) or not db <= DB_BAR:
+            failures.append(((fc, pitch, groups), got, db))
+    assert not failures, failures
