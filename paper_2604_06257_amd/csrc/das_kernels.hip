@@ -230,6 +230,9 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     const int64_t rec_bytes = (int64_t)kp.S * kp.F * kEB;
     const int lane_off = fbase * kEB;  // this thread's frames within a row
     const int row_bytes = kp.F * kEB;
+    // byte offset of this thread's first stage row (relative to the window start) and frames: the per-item
+    // offsets are then a wave-uniform product plus this, with no per-lane multiply in the loop
+    const int lane_row_off = row0 * row_bytes + lane_off;
     const bool fill_frames = fbase < kp.F;
     auto rsrc = [&](const int4& it) {
         const char* rec = reinterpret_cast<const char*>(iq) + ((int64_t)it.x * kp.E + it.y) * rec_bytes;
@@ -271,14 +274,16 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
         const int bb = bbase(ia);
         const bool in_b = ib.w > 0 && row0 >= bb;
         if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
-            const int4& it = in_b ? ib : ia;
-            const int r0 = in_b ? row0 - bb : row0;
+            // sample row of stage row r: ia.z + r (first window) or ib.z + r - bb (second window)
+            const int base_a = ia.z * row_bytes;         // wave-uniform
+            const int base_b = (ib.z - bb) * row_bytes;  // wave-uniform
+            const int base = (in_b ? base_b : base_a) + lane_row_off;
             // the record is uniform per thread but not per wave: two resources, each wave-uniform
             const __amdgpu_buffer_rsrc_t ra = rsrc(ia);
             const __amdgpu_buffer_rsrc_t rb = rsrc(ib.w > 0 ? ib : ia);
 #pragma unroll
             for (int j = 0; j <= RPT; ++j) {
-                const int off = (it.z + r0 + j) * row_bytes + lane_off;
+                const int off = base + j * row_bytes;
                 if (in_b) load_raw(rb, off, raw[j]);
                 else load_raw(ra, off, raw[j]);
             }
@@ -314,7 +319,7 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
         const bool use = live && (vox >= 0) && c.active && c.i0 >= it.z && c.i0 < it.z + it.w;
         c.row = use ? c.i0 - it.z + base : 0;
         c.t = it.x;
-        c.beta = use ? c.beta : 0.0f;
+        // beta stays: with zero weights the lane adds exact zeros whatever it interpolates
         c.cr = use ? c.cr : 0.0f;
         c.ci = use ? c.ci : 0.0f;
         return c;
