@@ -292,11 +292,12 @@ def test_one_plan_on_two_streams_concurrently():
 
 
 @pytest.mark.parametrize("T,F,dtype,force", [(3, 1, "c64", None), (4, 2, "c64", None), (2, 1, "f16", None),
-                                             (1, 1, "c64", None), (3, 1, "c64", "1,129,1"), (4, 2, "c64", "2,129,1")])
+                                             (1, 1, "c64", None), (3, 1, "c64", "1,129,1"), (4, 2, "c64", "2,129,1"),
+                                             (3, 1, "bf16", "1,65,2"), (4, 2, "c64", "2,257,2")])
 def test_per_transmit_output(T, F, dtype, force, monkeypatch):
     """das_execute_per_tx: each transmit's volume equals a one-transmit plan's output (bitwise for single-group
     plans) and the FP64 oracle's (T = 1) volume; the sum over transmits equals the compounded call.  `force`
-    pins a single-group variant (this small grid would otherwise take four element groups)."""
+    pins a variant (this small grid would otherwise take four element groups)."""
     if force:
         monkeypatch.setenv("DAS_VARIANT", force)
     iq, elem, vox, tx, p = small_case(500 + 10 * T + F, T=T, E=12, S=64, F=F, V=700)
@@ -307,7 +308,7 @@ def test_per_transmit_output(T, F, dtype, force, monkeypatch):
         fc, _, groups = plan.info()["kernel"]
         assert fc <= 2
         if force:
-            assert groups == 1
+            assert (fc, groups) == (int(force.split(",")[0]), int(force.split(",")[2]))
         y_t = plan.execute_per_tx(iq_t).cpu().numpy()
     assert y_t.shape == (T, vox.shape[0], F)
     iq_q = iq if dtype == "c64" else iq_t.float().cpu().numpy().view(np.complex64)[..., 0]
