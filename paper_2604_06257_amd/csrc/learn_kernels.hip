@@ -333,6 +333,147 @@ __global__ void upsample2_bwd_kernel(const uint16_t* __restrict__ gout, int gout
     gin[v * gin_stride + gin_coff + c] = f2bf(s);
 }
 
+// Vector forms of the resampling kernels and add_mask: 8 BF16 channels (16 bytes) per thread, for slices whose
+// channel count, stride and offset are multiples of 8.  Same arithmetic in the same order per element, so the
+// results are bitwise those of the scalar kernels.  Thread (x, y) of block (bx, by, d): x over (w, channel
+// group), h = 4 by + y, d = depth of the volume the thread writes.
+__device__ __forceinline__ void unpack8(const uint4& r, float (&f)[8]) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        f[2 * j] = __uint_as_float(w[j] << 16);
+        f[2 * j + 1] = __uint_as_float(w[j] & 0xffff0000u);
+    }
+}
+
+__device__ __forceinline__ uint4 pack8(const float (&f)[8]) {
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = (uint32_t)f2bf(f[2 * j]) | ((uint32_t)f2bf(f[2 * j + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+struct V8Pos {
+    int d, h, w, c;
+    bool ok;
+};
+
+__device__ __forceinline__ V8Pos v8_pos(const Vol& v, int C8) {
+    V8Pos p;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    p.h = blockIdx.y * blockDim.y + threadIdx.y;
+    p.d = blockIdx.z;
+    p.w = x / C8;
+    p.c = (x - p.w * C8) * 8;
+    p.ok = x < v.W * C8 && p.h < v.H;
+    return p;
+}
+
+__global__ void avgpool2_v8_kernel(const uint16_t* __restrict__ in, int in_stride, int in_coff,
+                                   uint16_t* __restrict__ out, int out_stride, int out_coff, Vol vo, int C8) {
+    const V8Pos p = v8_pos(vo, C8);
+    if (!p.ok) return;
+    const int Hi = 2 * vo.H, Wi = 2 * vo.W;
+    float s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] = 0.0f;
+    for (int q = 0; q < 8; ++q) {
+        const int64_t vi = ((int64_t)(2 * p.d + (q >> 2)) * Hi + (2 * p.h + ((q >> 1) & 1))) * Wi + (2 * p.w + (q & 1));
+        float f[8];
+        unpack8(*reinterpret_cast<const uint4*>(in + vi * in_stride + in_coff + p.c), f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += f[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] = 0.125f * s[j];
+    const int64_t v = ((int64_t)p.d * vo.H + p.h) * vo.W + p.w;
+    *reinterpret_cast<uint4*>(out + v * out_stride + out_coff + p.c) = pack8(s);
+}
+
+__global__ void avgpool2_bwd_v8_kernel(const uint16_t* __restrict__ gout, int gout_stride, int gout_coff,
+                                       uint16_t* __restrict__ gin, int gin_stride, int gin_coff, Vol vi, int C8,
+                                       int accumulate) {
+    const V8Pos p = v8_pos(vi, C8);
+    if (!p.ok) return;
+    const int64_t v = ((int64_t)p.d * vi.H + p.h) * vi.W + p.w;
+    const int64_t vp = ((int64_t)(p.d >> 1) * (vi.H >> 1) + (p.h >> 1)) * (vi.W >> 1) + (p.w >> 1);
+    float g[8];
+    unpack8(*reinterpret_cast<const uint4*>(gout + vp * gout_stride + gout_coff + p.c), g);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g[j] = 0.125f * g[j];
+    uint4* dst = reinterpret_cast<uint4*>(gin + v * gin_stride + gin_coff + p.c);
+    if (accumulate) {
+        float a[8];
+        unpack8(*dst, a);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) g[j] += a[j];
+    }
+    *dst = pack8(g);
+}
+
+__global__ void upsample2_v8_kernel(const uint16_t* __restrict__ in, int in_stride, int in_coff,
+                                    uint16_t* __restrict__ out, int out_stride, int out_coff, Vol vo, int C8) {
+    const V8Pos p = v8_pos(vo, C8);
+    if (!p.ok) return;
+    const int64_t v = ((int64_t)p.d * vo.H + p.h) * vo.W + p.w;
+    const int64_t vp = ((int64_t)(p.d >> 1) * (vo.H >> 1) + (p.h >> 1)) * (vo.W >> 1) + (p.w >> 1);
+    *reinterpret_cast<uint4*>(out + v * out_stride + out_coff + p.c) =
+        *reinterpret_cast<const uint4*>(in + vp * in_stride + in_coff + p.c);
+}
+
+__global__ void upsample2_bwd_v8_kernel(const uint16_t* __restrict__ gout, int gout_stride, int gout_coff,
+                                        uint16_t* __restrict__ gin, int gin_stride, int gin_coff,
+                                        const uint16_t* __restrict__ mask, int mask_stride, int mask_coff, Vol vi,
+                                        int C8) {
+    const V8Pos p = v8_pos(vi, C8);
+    if (!p.ok) return;
+    const int Ho = 2 * vi.H, Wo = 2 * vi.W;
+    float s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] = 0.0f;
+    for (int q = 0; q < 8; ++q) {
+        const int64_t vo = ((int64_t)(2 * p.d + (q >> 2)) * Ho + (2 * p.h + ((q >> 1) & 1))) * Wo + (2 * p.w + (q & 1));
+        float f[8];
+        unpack8(*reinterpret_cast<const uint4*>(gout + vo * gout_stride + gout_coff + p.c), f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += f[j];
+    }
+    const int64_t v = ((int64_t)p.d * vi.H + p.h) * vi.W + p.w;
+    if (mask) {
+        float m[8];
+        unpack8(*reinterpret_cast<const uint4*>(mask + v * mask_stride + mask_coff + p.c), m);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (!(m[j] > 0.0f)) s[j] = 0.0f;
+    }
+    *reinterpret_cast<uint4*>(gin + v * gin_stride + gin_coff + p.c) = pack8(s);
+}
+
+// add_mask over V voxels x C8 channel groups (V * C8 < 2^31, so the index split is a 32-bit division)
+__global__ void add_mask_v8_kernel(const uint16_t* __restrict__ a, int a_stride, int a_coff,
+                                   const uint16_t* __restrict__ b, int b_stride, int b_coff,
+                                   const uint16_t* __restrict__ mask, int m_stride, int m_coff,
+                                   uint16_t* __restrict__ g, int g_stride, int g_coff, int n, int C8) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int v32 = i / C8;
+    const int c = (i - v32 * C8) * 8;
+    const int64_t v = v32;
+    float x[8], y[8];
+    unpack8(*reinterpret_cast<const uint4*>(a + v * a_stride + a_coff + c), x);
+    unpack8(*reinterpret_cast<const uint4*>(b + v * b_stride + b_coff + c), y);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] += y[j];
+    if (mask) {
+        float m[8];
+        unpack8(*reinterpret_cast<const uint4*>(mask + v * m_stride + m_coff + c), m);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (!(m[j] > 0.0f)) x[j] = 0.0f;
+    }
+    *reinterpret_cast<uint4*>(g + v * g_stride + g_coff + c) = pack8(x);
+}
+
 // g[v][c] = (a[v][c] + b[v][c]) * (mask[v][c] > 0)   (bf16 slices)
 __global__ void add_mask_kernel(const uint16_t* __restrict__ a, int a_stride, int a_coff, const uint16_t* __restrict__ b,
                                 int b_stride, int b_coff, const uint16_t* __restrict__ mask, int m_stride, int m_coff,
@@ -495,6 +636,22 @@ int lfail(int st, const char* msg) {
 }
 bool al(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// The 8-channel vector kernels apply when every slice is 16-byte aligned (pointer, stride and offset) and the
+// volume fits their grid (x = W * C / 8 in 64-thread blocks, y = H in blocks of 4, z = D).
+bool v8_slice(const void* p, int stride, int coff) {
+    return p == nullptr || (reinterpret_cast<uintptr_t>(p) % 16 == 0 && stride % 8 == 0 && coff % 8 == 0);
+}
+
+bool v8_volume(int D, int H, int W, int c) {
+    return c % 8 == 0 && (int64_t)W * (c / 8) < (int64_t)1 << 30 && D <= 65535 && (H + 3) / 4 <= 65535;
+}
+
+dim3 v8_grid(int D, int H, int W, int c) {
+    return dim3((unsigned)(((int64_t)W * (c / 8) + 63) / 64), (unsigned)((H + 3) / 4), (unsigned)D);
+}
+
+const dim3 kV8Block(64, 4, 1);
 bool slices_ok(int s1, int o1, int s2, int o2, int c) { return c >= 1 && o1 >= 0 && o2 >= 0 && s1 >= o1 + c && s2 >= o2 + c; }
 bool even_dims(int D, int H, int W) { return D >= 2 && H >= 2 && W >= 2 && D % 2 == 0 && H % 2 == 0 && W % 2 == 0; }
 int launch_status(const char* what) {
@@ -684,6 +841,13 @@ int das_avgpool2(const void* in, int in_stride, int in_coff, void* out, int out_
     if (!in || !out) return lfail(DAS_EINVAL, "avgpool2: null pointer");
     if (!slices_ok(in_stride, in_coff, out_stride, out_coff, c) || Do < 1 || Ho < 1 || Wo < 1)
         return lfail(DAS_ESHAPE, "avgpool2: bad sizes or channel slices");
+    if (v8_volume(Do, Ho, Wo, c) && v8_slice(in, in_stride, in_coff) && v8_slice(out, out_stride, out_coff)) {
+        hipLaunchKernelGGL(learn::avgpool2_v8_kernel, v8_grid(Do, Ho, Wo, c), kV8Block, 0,
+                           reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(in), in_stride,
+                           in_coff, reinterpret_cast<uint16_t*>(out), out_stride, out_coff, learn::Vol{Do, Ho, Wo},
+                           c / 8);
+        return launch_status("avgpool2 launch failed");
+    }
     const int64_t n = (int64_t)Do * Ho * Wo * c;
     hipLaunchKernelGGL(learn::avgpool2_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(in), in_stride, in_coff,
@@ -696,6 +860,13 @@ int das_avgpool2_bwd(const void* gout, int gout_stride, int gout_coff, void* gin
     if (!gout || !gin) return lfail(DAS_EINVAL, "avgpool2_bwd: null pointer");
     if (!slices_ok(gout_stride, gout_coff, gin_stride, gin_coff, c) || !even_dims(Di, Hi, Wi))
         return lfail(DAS_ESHAPE, "avgpool2_bwd: input dimensions must be even and positive; bad channel slices");
+    if (v8_volume(Di, Hi, Wi, c) && v8_slice(gout, gout_stride, gout_coff) && v8_slice(gin, gin_stride, gin_coff)) {
+        hipLaunchKernelGGL(learn::avgpool2_bwd_v8_kernel, v8_grid(Di, Hi, Wi, c), kV8Block, 0,
+                           reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(gout), gout_stride,
+                           gout_coff, reinterpret_cast<uint16_t*>(gin), gin_stride, gin_coff, learn::Vol{Di, Hi, Wi},
+                           c / 8, accumulate);
+        return launch_status("avgpool2_bwd launch failed");
+    }
     const int64_t n = (int64_t)Di * Hi * Wi * c;
     hipLaunchKernelGGL(learn::avgpool2_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(gout), gout_stride,
@@ -709,6 +880,13 @@ int das_upsample2(const void* in, int in_stride, int in_coff, void* out, int out
     if (!in || !out) return lfail(DAS_EINVAL, "upsample2: null pointer");
     if (!slices_ok(in_stride, in_coff, out_stride, out_coff, c) || !even_dims(Do, Ho, Wo))
         return lfail(DAS_ESHAPE, "upsample2: output dimensions must be even and positive; bad channel slices");
+    if (v8_volume(Do, Ho, Wo, c) && v8_slice(in, in_stride, in_coff) && v8_slice(out, out_stride, out_coff)) {
+        hipLaunchKernelGGL(learn::upsample2_v8_kernel, v8_grid(Do, Ho, Wo, c), kV8Block, 0,
+                           reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(in), in_stride,
+                           in_coff, reinterpret_cast<uint16_t*>(out), out_stride, out_coff, learn::Vol{Do, Ho, Wo},
+                           c / 8);
+        return launch_status("upsample2 launch failed");
+    }
     const int64_t n = (int64_t)Do * Ho * Wo * c;
     hipLaunchKernelGGL(learn::upsample2_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(in), in_stride, in_coff,
@@ -722,6 +900,15 @@ int das_upsample2_bwd(const void* gout, int gout_stride, int gout_coff, void* gi
     if (!slices_ok(gout_stride, gout_coff, gin_stride, gin_coff, c) || Di < 1 || Hi < 1 || Wi < 1 ||
         (mask && (mask_stride < mask_coff + c || mask_coff < 0)))
         return lfail(DAS_ESHAPE, "upsample2_bwd: bad sizes or channel slices");
+    if (v8_volume(Di, Hi, Wi, c) && v8_slice(gout, gout_stride, gout_coff) && v8_slice(gin, gin_stride, gin_coff) &&
+        v8_slice(mask, mask_stride, mask_coff)) {
+        hipLaunchKernelGGL(learn::upsample2_bwd_v8_kernel, v8_grid(Di, Hi, Wi, c), kV8Block, 0,
+                           reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(gout), gout_stride,
+                           gout_coff, reinterpret_cast<uint16_t*>(gin), gin_stride, gin_coff,
+                           reinterpret_cast<const uint16_t*>(mask), mask_stride, mask_coff, learn::Vol{Di, Hi, Wi},
+                           c / 8);
+        return launch_status("upsample2_bwd launch failed");
+    }
     const int64_t n = (int64_t)Di * Hi * Wi * c;
     hipLaunchKernelGGL(learn::upsample2_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(gout), gout_stride,
@@ -736,6 +923,17 @@ int das_add_mask(const void* a, int a_stride, int a_coff, const void* b, int b_s
     if (V < 0 || !slices_ok(a_stride, a_coff, g_stride, g_coff, c) || b_stride < b_coff + c || b_coff < 0 ||
         (mask && (m_stride < m_coff + c || m_coff < 0)))
         return lfail(DAS_ESHAPE, "add_mask: bad sizes or channel slices");
+    if (c % 8 == 0 && V * (c / 8) < ((int64_t)1 << 31) && v8_slice(a, a_stride, a_coff) &&
+        v8_slice(b, b_stride, b_coff) && v8_slice(mask, m_stride, m_coff) && v8_slice(g, g_stride, g_coff)) {
+        const int n = (int)(V * (c / 8));
+        if (n == 0) return DAS_OK;
+        hipLaunchKernelGGL(learn::add_mask_v8_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
+                           reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(a), a_stride,
+                           a_coff, reinterpret_cast<const uint16_t*>(b), b_stride, b_coff,
+                           reinterpret_cast<const uint16_t*>(mask), m_stride, m_coff, reinterpret_cast<uint16_t*>(g),
+                           g_stride, g_coff, n, c / 8);
+        return launch_status("add_mask launch failed");
+    }
     hipLaunchKernelGGL(learn::add_mask_kernel, dim3(blocks_for(V * c, 256)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint16_t*>(a), a_stride, a_coff,
                        reinterpret_cast<const uint16_t*>(b), b_stride, b_coff, reinterpret_cast<const uint16_t*>(mask),

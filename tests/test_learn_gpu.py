@@ -132,10 +132,12 @@ def test_conv3d_wgrad_matches_oracle(D, H, W, cin, cout, chunk):
     assert torch.equal(dw, dw2)
 
 
-def test_pool_upsample_and_masks_match_oracle():
+@pytest.mark.parametrize("Di,Hi,Wi,c", [(6, 4, 8, 16), (6, 4, 8, 12), (10, 6, 14, 16), (10, 6, 14, 24)])
+def test_pool_upsample_and_masks_match_oracle(Di, Hi, Wi, c):
+    """Channel counts that are multiples of 8 take the 16-byte vector kernels, others the scalar ones; the
+    10 x 6 x 14 volume leaves partial blocks along W and H."""
     L = _learn()
-    r = np.random.default_rng(9)
-    Di, Hi, Wi, c = 6, 4, 8, 16
+    r = np.random.default_rng(9 + c)
     x = bf16_round(r.standard_normal((Di, Hi, Wi, c)))
     g = bf16_round(r.standard_normal((Di // 2, Hi // 2, Wi // 2, c)))
     dims_o = (Di // 2, Hi // 2, Wi // 2)
@@ -149,7 +151,7 @@ def test_pool_upsample_and_masks_match_oracle():
     L.avgpool2_bwd(to_dev_bf16(g), gi, (Di, Hi, Wi), accumulate=True)
     np.testing.assert_array_equal(host(gi).reshape(x.shape), bf16_round(2 * prev))
     # upsample into a channel slice, and its masked gradient
-    u = torch.zeros((Di * Hi * Wi, 24), dtype=torch.bfloat16, device=DEV)
+    u = torch.zeros((Di * Hi * Wi, c + 8), dtype=torch.bfloat16, device=DEV)
     L.upsample2(to_dev_bf16(g), L.Slice(u, 8, c), (Di, Hi, Wi))
     np.testing.assert_array_equal(host(u)[:, 8:].reshape(x.shape), U.upsample2(g))
     assert not host(u)[:, :8].any()
