@@ -491,7 +491,7 @@ __global__ void mse_kernel(const float* __restrict__ net, int net_stride, const 
     red[threadIdx.x] = l;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const float2* __restrict__ y
     red[threadIdx.x] = l;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void rms_kernel(const float* __restrict__ part
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void frame_peak_kernel(const float* __restrict
     red[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
     if (threadIdx.x == 0) peak[f] = red[0];
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
         red[threadIdx.x] = off;
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
             __syncthreads();
         }
         const double off_sum = red[0];
@@ -158,14 +158,14 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
         red[threadIdx.x] = tot;
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
             __syncthreads();
         }
         if (threadIdx.x == 0) done = !(off_sum > 1e-28 * red[0]);  // off-diagonal norm below 1e-14 of the total
         __syncthreads();
         if (done) break;
         for (int s = 0; s < n - 1; ++s) {
-            if (threadIdx.x < half) {
+            if ((int)threadIdx.x < half) {
                 const int k = threadIdx.x;
                 int p = rr(k, s, n), q = rr(n - 1 - k, s, n);
                 if (p > q) {
