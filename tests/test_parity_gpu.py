@@ -244,7 +244,8 @@ def test_binding_rejects_wrong_shapes_and_dtypes():
 # ------------------------------------------------------- 16-bit IQ storage
 @pytest.mark.parametrize("kind", ["f16", "bf16"])
 def test_16bit_iq_parity_and_storage_error(kind):
-    cfg = make_config("c2", n_frames=8)
+    """The c2 configuration the benchmark times (32 frames), with IQ stored as FP16 / BF16."""
+    cfg = make_config("c2")
     p = oracle_params(cfg)
     vox, iq = cfg["vox"], cfg["iq"]
     tx = tx_table(vox, cfg["angles"], p["c"])
@@ -258,7 +259,7 @@ def test_16bit_iq_parity_and_storage_error(kind):
     # against the full-precision input: the storage error, reported in dB
     ref = oracle.das(iq, cfg["elem"], vox[idx], tx[:, idx], **p)
     db = oracle.nrmse_db(y[idx], ref)
-    print(kind, "storage error vs complex64 input: %.1f dB" % db)
+    print(kind, info["kernel"], "storage error vs complex64 input: %.1f dB" % db)
     assert db <= (-65.0 if kind == "f16" else -45.0)
 
 
