@@ -31,7 +31,12 @@ WORKLOADS = {
     "c2_251": "paper-exact grid of the rotating-disk benchmark: as c2 with 251 x 251 voxels",
     "c1": "2D plane wave, 128-el linear array, 1 transmit, 1 frame x 1024 samples, 128 x 128 grid, f# 1.5",
     "c3": "3D: 32 x 32 matrix array, 5 elevation plane waves, 8 frames x 2048 samples, 96^3 grid, f# 1.0",
+    "c3_f1": "c3 with 1 frame: the per-GPU share when c3's frames are split over 8 GPUs",
+    "c3_v8": "c3 on the central 12 of its 96 x columns (110592 voxels, all 8 frames): the heaviest per-GPU share "
+             "when c3's voxels are split over 8 GPUs in lateral slabs",
 }
+# workloads that are a listed configuration with other settings: (config, make_config overrides, x-column slice)
+WORKLOAD_CONFIG = {"c3_f1": ("c3", {"n_frames": 1}, None), "c3_v8": ("c3", {}, (42, 54))}
 FLOP_PER_POINT = 16          # two complex multiply-accumulates per (voxel, element, transmit, frame)
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
 PAPER_PTS_PER_S = 258052096 / 0.23e-3   # RTX 5090, 251 x 251 rotating disk (context only)
@@ -235,7 +240,11 @@ def main():
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    cfg = make_config(args.workload)
+    name, overrides, xcols = WORKLOAD_CONFIG.get(args.workload, (args.workload, {}, None))
+    cfg = make_config(name, **overrides)
+    if xcols is not None:
+        xs = np.unique(cfg["vox"][:, 0])
+        cfg["vox"] = np.ascontiguousarray(cfg["vox"][np.isin(cfg["vox"][:, 0], xs[xcols[0]:xcols[1]])])
     p = cfg["params"]
     iq_np = cfg["iq"]
     T, E, S, F = iq_np.shape

@@ -436,7 +436,9 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
         // Work items per tile: the non-empty (t, e) windows, cut into pieces of at
         // most pitch - 1 rows, element-major so consecutive items share the
         // receive geometry.
-        const das::Variant var = das::choose_variant(p->n_frames, plan->max_window, tl.n_tiles);
+        // average (transmit, element) pairs with a non-empty window per tile: processed triples per valid slot
+        const double items_per_tile = p->n_vox > 0 ? (double)plan->processed_triples / (double)p->n_vox : 0.0;
+        const das::Variant var = das::choose_variant(p->n_frames, plan->max_window, tl.n_tiles, items_per_tile);
         d.fc = var.fc;
         d.pitch = var.pitch;
         d.groups = var.groups;

@@ -52,11 +52,12 @@ struct PlanDev {
 // regions interleaved so that workgroup w runs on XCD w % 8.
 std::vector<int32_t> order_units(const Tiling& tl, const std::vector<int32_t>& item_off, int chunks, bool xcd_runs);
 
-// Kernel variant for F frames and the largest tile window (rows).
+// Kernel variant for F frames, the largest tile window (rows), the tile count and the average number of
+// (transmit, element) items per tile.
 struct Variant {
     int fc, pitch, groups;
 };
-Variant choose_variant(int frames, int max_window, int64_t n_tiles);
+Variant choose_variant(int frames, int max_window, int64_t n_tiles, double items_per_tile);
 
 // The compiled variants as (fc, pitch, groups) triples: writes min(count, capacity) of them to out (when not
 // null) and returns the count.

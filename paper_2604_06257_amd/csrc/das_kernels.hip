@@ -531,8 +531,10 @@ static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, v
 //  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks; 5-8 frames take 8-frame chunks
 //    unless the grid is large (then 4-frame chunks, which hold 8 waves per SIMD);
 //  - with fewer workgroups than CUs (256), the frame chunk is halved until there are enough;
-//  - a launch should then hold about 6144 waves (FC <= 4) or 2560 waves (FC >= 8): element groups
-//    (4 waves each) are added until it does, up to 4 groups (16 waves per workgroup).
+//  - a launch should then hold about 6144 waves (FC <= 4) or 2560 waves (FC >= 8), or 8192 when tiles carry
+//    1024 or more (transmit, element) items on average (3D, many elements: a c3 slab of 576 tiles ran 2.09 ms
+//    with 9216 waves and 2.67 ms with 4608): element groups (4 waves each) are added until it does, up to 4
+//    groups (16 waves per workgroup).
 static bool variant_exists(int fc, int pitch, int g) {
 #define DAS_HAS(FC_, P_, G_) \
     if (FC_ == fc && P_ == pitch && G_ == g) return true;
@@ -551,7 +553,7 @@ static int pitch_at_least(int fc, int min_pitch, int g) {
     return best;
 }
 
-Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
+Variant choose_variant(int frames, int max_window, int64_t n_tiles, double items_per_tile) {
     int fc;
     if (frames >= 32) fc = (n_tiles < 512) ? 16 : 32;
     else if (frames > 8) fc = 16;
@@ -578,7 +580,7 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles) {
     DAS_VARIANTS(DAS_PICK)
 #undef DAS_PICK
     if (best.fc == 0 || best.fc > 16) return best;
-    const int64_t target = best.fc <= 4 ? 6144 : 2560;
+    const int64_t target = items_per_tile >= 1024.0 ? 8192 : (best.fc <= 4 ? 6144 : 2560);
     for (int g = base_g; g <= 4; g *= 2) {
         const int p = pitch_at_least(best.fc, best.pitch, g);
         if (p != 0 && (n_tiles * chunks(best.fc) * 4 * g >= target || g == 4)) return Variant{best.fc, p, g};
