@@ -34,9 +34,12 @@ WORKLOADS = {
     "c3_f1": "c3 with 1 frame: the per-GPU share when c3's frames are split over 8 GPUs",
     "c3_v8": "c3 on the central 12 of its 96 x columns (110592 voxels, all 8 frames): the heaviest per-GPU share "
              "when c3's voxels are split over 8 GPUs in lateral slabs",
+    "c3_v4f4": "c3 on the central 24 x columns with 4 frames: the heaviest per-GPU share of 4 slabs x 2 frame groups",
+    "c3_v2f2": "c3 on the central 48 x columns with 2 frames: the heaviest per-GPU share of 2 slabs x 4 frame groups",
 }
 # workloads that are a listed configuration with other settings: (config, make_config overrides, x-column slice)
-WORKLOAD_CONFIG = {"c3_f1": ("c3", {"n_frames": 1}, None), "c3_v8": ("c3", {}, (42, 54))}
+WORKLOAD_CONFIG = {"c3_f1": ("c3", {"n_frames": 1}, None), "c3_v8": ("c3", {}, (42, 54)),
+                   "c3_v4f4": ("c3", {"n_frames": 4}, (36, 60)), "c3_v2f2": ("c3", {"n_frames": 2}, (24, 72))}
 FLOP_PER_POINT = 16          # two complex multiply-accumulates per (voxel, element, transmit, frame)
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
 PAPER_PTS_PER_S = 258052096 / 0.23e-3   # RTX 5090, 251 x 251 rotating disk (context only)
