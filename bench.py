@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--cpu-voxels", type=int, default=None, help="voxels in the oracle sample (default: all)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a torch copy of this many GiB (for HBM counter calibration)")
+    ap.add_argument("--post", action="store_true",
+                    help="also time B-mode and Power Doppler (SVD clutter filter, rank 1) on the beamformed frames")
     ap.add_argument("--sweep", choices=("voxels", "elements", "frames"), default=None,
                     help="print one JSON line per size along this axis instead of the benchmark line")
     args = ap.parse_args()
@@ -334,6 +336,25 @@ def main():
             del iq16
         var["iq_range"] = iq16_range(iq_np)
         result["iq16_variants"] = var
+    if args.post:
+        from paper_2604_06257_amd import post
+        plan.execute(iq, out)
+        pm = {}
+        for name, fn in (("bmode_60db", lambda: post.bmode(out, 60.0)),
+                         ("power_doppler_k1", lambda: post.power_doppler(out, 1))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn()
+            e1.record()
+            e1.synchronize()
+            pm[name] = e0.elapsed_time(e1) / 20
+        pm["beamform"] = result["ms_per_step"]
+        result["post_ms"] = pm
     if args.copy_calibration > 0:
         n = int(args.copy_calibration * (1 << 30)) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -69,7 +69,7 @@ __global__ void bmode_kernel(const float2* __restrict__ y, int64_t n, int F, con
     out[i] = db;
 }
 
-// part[b][i][j] = sum over the block's voxel chunk of conj(y[v][i]) y[v][j]   (float64 complex, F <= 32)
+// part[i F + j][b] = sum over block b's voxel chunk of conj(y[v][i]) y[v][j]   (float64 complex, F <= 32)
 __global__ __launch_bounds__(256) void gram_partial_kernel(const float2* __restrict__ y, int64_t V, int F,
                                                            int64_t chunk, double2* __restrict__ part) {
     __shared__ float2 tile[64 * kMaxF];
@@ -103,8 +103,27 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const float2* __restr
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int pr = threadIdx.x + 256 * r;
-        if (pr < npair) part[(int64_t)blockIdx.x * npair + pr] = acc[r];
+        if (pr < npair) part[(int64_t)pr * gridDim.x + blockIdx.x] = acc[r];  // entry-major: [pair][block]
     }
+}
+
+// G[e] = sum_b part[e][b]: one wave per entry; lane l adds blocks l, l + 64, ... in order, then a fixed xor
+// butterfly over the 64 lanes (deterministic)
+__global__ __launch_bounds__(64) void gram_reduce_kernel(const double2* __restrict__ part, int nb,
+                                                         double2* __restrict__ g) {
+    const int e = blockIdx.x, lane = threadIdx.x;
+    const double2* src = part + (int64_t)e * nb;
+    double re = 0.0, im = 0.0;
+    for (int b = lane; b < nb; b += 64) {
+        const double2 x = src[b];
+        re += x.x;
+        im += x.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+    }
+    if (lane == 0) g[e] = make_double2(re, im);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -116,20 +135,24 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 // Round-robin position: element 0 stays, the others rotate by one place per step.
 __device__ __forceinline__ int rr(int i, int s, int n) { return i == 0 ? 0 : ((i - 1 + s) % (n - 1)) + 1; }
 
-// G = sum_b part[b]; eigenvectors by parallel cyclic Jacobi; vec[f][j] = eigenvector j (descending eigenvalues)
-__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ part, int nb, int F,
-                                                     double2* __restrict__ vec, double* __restrict__ eval,
-                                                     int max_sweeps) {
+// G = sum_b part[b]; eigenvectors by parallel cyclic Jacobi; vec[f][j] = eigenvector j (descending eigenvalues).
+// NT threads (256 measured faster than one 64-lane wave: the update pass dominates a step).  The pair schedule
+// and every thread's update indices are formed once, outside the sweeps.
+template <int NT>
+__global__ __launch_bounds__(NT) void jacobi_kernel(const double2* __restrict__ part, int nb, int F,
+                                                    double2* __restrict__ vec, double* __restrict__ eval,
+                                                    int max_sweeps) {
+    constexpr int kQItems = (kMaxF / 2 * kMaxF + NT - 1) / NT;  // Q-update items per thread
     __shared__ double2 A[kMaxF][kMaxF + 1];
     __shared__ double2 Q[kMaxF][kMaxF + 1];
-    __shared__ double2 U[kMaxF / 2][4];  // u_pp, u_pq, u_qp, u_qq per pair
-    __shared__ int P[kMaxF / 2][2];
-    __shared__ double red[256];
+    __shared__ double2 U[kMaxF / 2][4];       // u_pp, u_pq, u_qp, u_qq per pair
+    __shared__ int PT[kMaxF - 1][kMaxF / 2][2];  // round-robin pairs (p < q) of every step of a sweep
     __shared__ int order[kMaxF];
-    __shared__ int done;
+    __shared__ int rotated;
+    __shared__ double floor2;  // (1e-16 trace G)^2: rounding leaves off-diagonal entries near eps * |G|
     const int n = F + (F & 1);  // even; index F is a dummy when F is odd
     const int half = n / 2;
-    for (int pr = threadIdx.x; pr < n * n; pr += 256) {
+    for (int pr = threadIdx.x; pr < n * n; pr += NT) {
         const int i = pr / n, j = pr % n;
         double2 g = make_double2(0.0, 0.0);
         if (i < F && j < F)
@@ -137,52 +160,56 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
         A[i][j] = g;
         Q[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
+    for (int w = threadIdx.x; w < (n - 1) * half; w += NT) {
+        const int st = w / half, k = w % half;
+        int p = rr(k, st, n), q = rr(n - 1 - k, st, n);
+        if (p > q) {
+            const int t = p;
+            p = q;
+            q = t;
+        }
+        PT[st][k][0] = p;
+        PT[st][k][1] = q;
+    }
+    // this thread's work in the update pass: one 2 x 2 block of pairs (bi, bj) and up to kQItems (pair, row) of Q
+    const int nblk = half * half, nq = half * n;
+    const bool has_blk = (int)threadIdx.x < nblk;
+    const int bi = has_blk ? (int)threadIdx.x / half : 0, bj = has_blk ? (int)threadIdx.x - bi * half : 0;
+    int qk[kQItems], qi[kQItems];
+#pragma unroll
+    for (int r = 0; r < kQItems; ++r) {
+        const int w = threadIdx.x + r * NT;
+        qk[r] = w < nq ? w / n : -1;
+        qi[r] = w < nq ? w % n : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < F; ++i) tr += fabs(A[i][i].x);
+        floor2 = 1e-32 * tr * tr;
+    }
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // convergence: off-diagonal energy against the total
-        double off = 0.0, tot = 0.0;
-        for (int pr = threadIdx.x; pr < n * n; pr += 256) {
-            const int i = pr / n, j = pr % n;
-            const double m = A[i][j].x * A[i][j].x + A[i][j].y * A[i][j].y;
-            tot += m;
-            if (i != j) off += m;
-        }
-        red[threadIdx.x] = off;
+        // a sweep that rotates no pair ends the iteration (every |a_pq| is at rounding level)
+        if (threadIdx.x == 0) rotated = 0;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        const double off_sum = red[0];
-        __syncthreads();
-        red[threadIdx.x] = tot;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) done = !(off_sum > 1e-28 * red[0]);  // off-diagonal norm below 1e-14 of the total
-        __syncthreads();
-        if (done) break;
         for (int s = 0; s < n - 1; ++s) {
             if ((int)threadIdx.x < half) {
                 const int k = threadIdx.x;
-                int p = rr(k, s, n), q = rr(n - 1 - k, s, n);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                P[k][0] = p;
-                P[k][1] = q;
+                const int p = PT[s][k][0], q = PT[s][k][1];
                 double2 upp = make_double2(1.0, 0.0), upq = make_double2(0.0, 0.0), uqp = upq, uqq = upp;
                 const double2 apq = A[p][q];
-                const double b = sqrt(apq.x * apq.x + apq.y * apq.y);
-                if (q < F && b > 0.0) {
-                    const double e_re = apq.x / b, e_im = -apq.y / b;  // e = exp(-i arg a_pq)
-                    const double tau = (A[q][q].x - A[p][p].x) / (2.0 * b);
+                const double b2 = apq.x * apq.x + apq.y * apq.y;
+                const double app = A[p][p].x, aqq = A[q][q].x;
+                // rotate unless |a_pq| is negligible against its diagonal pair (|a_pq| <= 1e-15 sqrt(a_pp a_qq))
+                // or at the rounding floor of the whole matrix (|a_pq| <= 1e-16 trace G)
+                if (q < F && b2 > floor2 && b2 > 1e-30 * fabs(app * aqq)) {
+                    rotated = 1;
+                    const double rb = rsqrt(b2);                       // 1 / |a_pq|
+                    const double e_re = apq.x * rb, e_im = -apq.y * rb;  // e = exp(-i arg a_pq)
+                    const double tau = 0.5 * (aqq - app) * rb;
                     const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+                    const double c = rsqrt(1.0 + t * t), sn = t * c;
                     // U = diag(1, e) [[c, s], [-s, c]]
                     upp = make_double2(c, 0.0);
                     upq = make_double2(sn, 0.0);
@@ -195,44 +222,54 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
                 U[k][3] = uqq;
             }
             __syncthreads();
-            // rows: A <- U^H A
-            for (int w = threadIdx.x; w < half * n; w += 256) {
-                const int k = w / n, j = w % n, p = P[k][0], q = P[k][1];
-                const double2 ap = A[p][j], aq = A[q][j];
-                A[p][j] = cadd(cmul(cconj(U[k][0]), ap), cmul(cconj(U[k][2]), aq));
-                A[q][j] = cadd(cmul(cconj(U[k][1]), ap), cmul(cconj(U[k][3]), aq));
+            // A <- U^H A U block by block: the 2 x 2 block of pairs (i, j) becomes U_i^H B U_j (the row update,
+            // rounded, then the column update, as two separate passes would compute it); Q <- Q U
+            if (has_blk) {
+                const int pi = PT[s][bi][0], qi_ = PT[s][bi][1], pj = PT[s][bj][0], qj = PT[s][bj][1];
+                const double2 a00 = A[pi][pj], a01 = A[pi][qj], a10 = A[qi_][pj], a11 = A[qi_][qj];
+                const double2 t00 = cadd(cmul(cconj(U[bi][0]), a00), cmul(cconj(U[bi][2]), a10));
+                const double2 t01 = cadd(cmul(cconj(U[bi][0]), a01), cmul(cconj(U[bi][2]), a11));
+                const double2 t10 = cadd(cmul(cconj(U[bi][1]), a00), cmul(cconj(U[bi][3]), a10));
+                const double2 t11 = cadd(cmul(cconj(U[bi][1]), a01), cmul(cconj(U[bi][3]), a11));
+                A[pi][pj] = cadd(cmul(t00, U[bj][0]), cmul(t01, U[bj][2]));
+                A[pi][qj] = cadd(cmul(t00, U[bj][1]), cmul(t01, U[bj][3]));
+                A[qi_][pj] = cadd(cmul(t10, U[bj][0]), cmul(t11, U[bj][2]));
+                A[qi_][qj] = cadd(cmul(t10, U[bj][1]), cmul(t11, U[bj][3]));
             }
-            __syncthreads();
-            // columns: A <- A U, Q <- Q U
-            for (int w = threadIdx.x; w < half * n; w += 256) {
-                const int k = w / n, i = w % n, p = P[k][0], q = P[k][1];
-                const double2 ap = A[i][p], aq = A[i][q];
-                A[i][p] = cadd(cmul(ap, U[k][0]), cmul(aq, U[k][2]));
-                A[i][q] = cadd(cmul(ap, U[k][1]), cmul(aq, U[k][3]));
+#pragma unroll
+            for (int r = 0; r < kQItems; ++r) {
+                if (qk[r] < 0) continue;
+                const int k = qk[r], i = qi[r], p = PT[s][k][0], q = PT[s][k][1];
                 const double2 qp = Q[i][p], qq = Q[i][q];
                 Q[i][p] = cadd(cmul(qp, U[k][0]), cmul(qq, U[k][2]));
                 Q[i][q] = cadd(cmul(qp, U[k][1]), cmul(qq, U[k][3]));
             }
             __syncthreads();
         }
+        // every thread reads the flag before thread 0 may reset it for the next sweep, so all leave together
+        const bool again = rotated != 0;
+        __syncthreads();
+        if (!again) break;
     }
-    if (threadIdx.x == 0) {  // eigenvalues in descending order (stable: ties keep index order)
-        for (int i = 0; i < F; ++i) order[i] = i;
-        for (int i = 0; i < F; ++i) {
-            int best = i;
-            for (int j = i + 1; j < F; ++j)
-                if (A[order[j]][order[j]].x > A[order[best]][order[best]].x) best = j;
-            const int t = order[i];
-            order[i] = order[best];
-            order[best] = t;
+    // eigenvalues in descending order, ties in index order: each thread ranks one eigenvalue (order starts as
+    // the identity so that every entry is a valid index even if a NaN makes two ranks collide)
+    for (int i = threadIdx.x; i < F; i += NT) order[i] = i;
+    __syncthreads();
+    for (int i = threadIdx.x; i < F; i += NT) {
+        const double di = A[i][i].x;
+        int rank = 0;
+        for (int j = 0; j < F; ++j) {
+            const double dj = A[j][j].x;
+            rank += (dj > di || (dj == di && j < i)) ? 1 : 0;
         }
+        order[rank] = i;
     }
     __syncthreads();
-    for (int pr = threadIdx.x; pr < F * F; pr += 256) {
+    for (int pr = threadIdx.x; pr < F * F; pr += NT) {
         const int f = pr / F, j = pr % F;
         vec[pr] = Q[f][order[j]];
     }
-    for (int j = threadIdx.x; j < F; j += 256) eval[j] = A[order[j]][order[j]].x;
+    for (int j = threadIdx.x; j < F; j += NT) eval[j] = A[order[j]][order[j]].x;
 }
 
 // pd[v] = |c_v|^2 - sum_{j<k} |sum_f c_v[f] vec[f][j]|^2  (float64), clamped at 0
@@ -273,9 +310,10 @@ int pfail(int st, const char* msg) {
 int post_launch_status(const char* what) {
     return hipGetLastError() == hipSuccess ? DAS_OK : pfail(DAS_EHIP, what);
 }
+// voxels per Gram partial block: enough blocks (up to 2048) to fill the chip, at least one 64-voxel tile each
 int64_t gram_chunk(int64_t V) {
-    const int64_t c = (V + 511) / 512;
-    return c < 1024 ? 1024 : c;
+    const int64_t c = (V + 2047) / 2048;
+    return c < 64 ? 64 : c;
 }
 }  // namespace
 
@@ -311,7 +349,7 @@ int das_bmode(const void* y, int64_t V, int F, float dynamic_range_db, float* ou
 int64_t das_power_doppler_work(int64_t V, int F) {
     if (V < 1 || F < 1) return 0;
     const int64_t nb = (V + gram_chunk(V) - 1) / gram_chunk(V);
-    return 2 * (nb * F * F + (int64_t)F * F) + F;
+    return 2 * (nb * F * F + 2 * (int64_t)F * F) + F;  // partial Gram matrices, the sum, eigenvectors; eigenvalues
 }
 
 int das_power_doppler(const void* y, int64_t V, int F, int n_clutter, float* pd, double* work, int64_t work_doubles,
@@ -325,10 +363,12 @@ int das_power_doppler(const void* y, int64_t V, int F, int n_clutter, float* pd,
     const int64_t chunk = gram_chunk(V);
     const int nb = (int)((V + chunk - 1) / chunk);
     double2* part = reinterpret_cast<double2*>(work);
-    double2* vec = part + (int64_t)nb * F * F;
+    double2* gram = part + (int64_t)nb * F * F;
+    double2* vec = gram + (int64_t)F * F;
     double* eval = reinterpret_cast<double*>(vec + (int64_t)F * F);
     hipLaunchKernelGGL(post::gram_partial_kernel, dim3(nb), dim3(256), 0, s, yy, V, F, chunk, part);
-    hipLaunchKernelGGL(post::jacobi_kernel, dim3(1), dim3(256), 0, s, part, nb, F, vec, eval, 40);
+    hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, gram);
+    hipLaunchKernelGGL(post::jacobi_kernel<256>, dim3(1), dim3(256), 0, s, gram, 1, F, vec, eval, 40);
     hipLaunchKernelGGL(post::pd_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, yy, V, F, n_clutter, vec,
                        pd);
     return post_launch_status("power_doppler launch failed");
