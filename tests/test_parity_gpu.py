@@ -384,3 +384,33 @@ def test_every_kernel_variant(kind, monkeypatch):
         if got != (fc, pitch, groups) or not db <= DB_BAR:
             failures.append(((fc, pitch, groups), got, db))
     assert not failures, failures
+
+
+@pytest.mark.parametrize("kind", ["c64", "f16", "bf16"])
+def test_every_per_transmit_variant(kind, monkeypatch):
+    """Every variant that has a per-transmit form (1 or 2 frames per workgroup), forced, for each IQ type: each
+    transmit's volume against the FP64 oracle of that transmit alone on the same (quantised) samples."""
+    T, F = 3, 2
+    iq, elem, vox, tx, p = small_case(1300, T=T, E=16, S=80, F=F, V=600, depth=(0.3e-3, 2.0e-3))
+    if kind == "c64":
+        iq_q, x_host = iq, None
+    else:
+        dt = torch.float16 if kind == "f16" else torch.bfloat16
+        x_host = torch.view_as_real(torch.from_numpy(iq.astype(np.complex64))).to(dt).contiguous()
+        iq_q = x_host.float().numpy().view(np.complex64)[..., 0]
+    refs = [oracle.das(iq_q[t:t + 1], elem, vox, tx[t:t + 1], **p) for t in range(T)]
+    params = das.Params(n_tx=T, n_elem=16, n_samples=80, n_frames=F, n_vox=vox.shape[0], sound_speed=p["c"],
+                        fs=p["fs"], f_demod=p["fd"], t0=p["t0"], f_number=p["f_number"], tukey_alpha=p["tukey_alpha"])
+    x = dev(iq_q.astype(np.complex64)) if kind == "c64" else x_host.cuda()
+    failures = []
+    for fc, pitch, groups in das.kernel_variants():
+        if fc > 2:
+            continue
+        monkeypatch.setenv("DAS_VARIANT", "%d,%d,%d" % (fc, pitch, groups))
+        with das.Plan(params, dev(elem), dev(vox), dev(tx)) as plan:
+            got = plan.info()["kernel"]
+            y = plan.execute_per_tx(x).cpu().numpy()
+        dbs = [oracle.nrmse_db(y[t], refs[t]) for t in range(T)]
+        if got != (fc, pitch, groups) or not max(dbs) <= DB_BAR:
+            failures.append(((fc, pitch, groups), got, dbs))
+    assert not failures, failures
