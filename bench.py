@@ -172,7 +172,8 @@ def iq16_range(iq):
     when stored as float16 / bfloat16 (round to nearest even; overflow needs max >= 65504 for float16)."""
     ri = np.abs(np.stack([iq.real, iq.imag]).ravel().astype(np.float32))
     nz = ri[ri > 0]
-    f16 = np.abs(nz.astype(np.float16).astype(np.float32))
+    with np.errstate(over="ignore"):  # components beyond float16's range become inf (reported by fits_fp16)
+        f16 = np.abs(nz.astype(np.float16).astype(np.float32))
     sub16 = float(np.mean((f16 > 0) & (f16 < 2.0 ** -14))) if nz.size else 0.0
     # bfloat16 keeps float32's exponent range: subnormal below 2^-126
     subbf = float(np.mean(nz < 2.0 ** -126)) if nz.size else 0.0

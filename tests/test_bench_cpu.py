@@ -1,0 +1,52 @@
+"""Host-side checks of bench.py: argument contract, the traffic record's source-hash guard, workload table and
+the 16-bit range report (no GPU needed)."""
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from synth.configs import CONFIGS  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--gpus 2" in r.stderr and r.stdout == ""
+
+
+def test_traffic_record_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
+    h = bench.kernel_source_hash()
+    assert h == bench.kernel_source_hash() and len(h) == 64
+    rec = tmp_path / "traffic.txt"
+    rec.write_text("# comment\nsource_sha256 %s\nc2 fetch_kib 1.0 write_kib 2.0 read_bytes 100 write_bytes 20\n" % h)
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
+    assert bench.measured_traffic("c2") == 120
+    assert bench.measured_traffic("c1") is None  # no record for this workload
+    rec.write_text("source_sha256 %s\nc2 fetch_kib 1.0 write_kib 2.0 read_bytes 100 write_bytes 20\n" % ("0" * 64))
+    assert bench.measured_traffic("c2") is None  # the kernel sources changed since the counters were taken
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic("c2") is None
+
+
+def test_workload_table():
+    for name, (base, overrides, xcols) in bench.WORKLOAD_CONFIG.items():
+        assert name in bench.WORKLOADS and base in CONFIGS
+        assert set(overrides) <= {"n_frames"}
+        assert xcols is None or 0 <= xcols[0] < xcols[1] <= 96
+    for name in bench.WORKLOADS:
+        assert name in CONFIGS or name in bench.WORKLOAD_CONFIG
+
+
+def test_iq16_range_report():
+    iq = np.array([1.0 + 2.0j, 70000.0 - 1e-6j, 0.0, 1e-40 + 0j], dtype=np.complex64)
+    r = bench.iq16_range(iq)
+    assert r["max_abs_component"] == 70000.0 and not r["fits_fp16"]
+    assert 0.0 < r["fp16_flushed_to_zero_fraction"] < 1.0
+    assert r["bf16_subnormal_fraction"] > 0.0  # 1e-40 is below float32's normal range
