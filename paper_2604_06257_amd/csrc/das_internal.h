@@ -63,9 +63,10 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles, double items
 // null) and returns the count.
 int list_variants(int32_t* out, int capacity);
 
-// Whether a variant stages two items per step (the plan packs stages only for such variants): with 8 or
-// more frames per workgroup the saved fill and barrier outweigh the extra registers.
-constexpr bool stage_pairs(int fc) { return fc >= 8; }
+// Whether a variant stages two items per step (the plan packs stages only for such variants): with 16 or
+// more frames per workgroup the saved fill and barrier outweigh the extra registers.  At 8 frames the unpaired
+// variant at 6 waves per SIMD beats the paired one at 4 (c3: 5.13 against 6.78 ms).
+constexpr bool stage_pairs(int fc) { return fc >= 16; }
 
 // Window rows each fill thread stages for a variant (the largest over the IQ types: complex64, which packs
 // the fewest frames into a 16-byte load); the second window of a stage starts at a multiple of it.

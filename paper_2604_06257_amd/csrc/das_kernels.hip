@@ -162,12 +162,13 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 // Waves per SIMD that the LDS footprint allows (the compiler may then spend
 // registers on instruction-level parallelism instead of occupancy).
 // Variants that stage two items per step are capped so that the second item's registers (coefficients,
-// transmit time) fit without spilling: 4 waves (128 VGPRs) up to 16 frames, 3 (168) for 32.
+// transmit time) fit without spilling: 4 waves (128 VGPRs) for 16 frames, 3 (168) for 32; unpaired 8-frame
+// variants run at 6 waves (85 VGPRs: their 16 accumulators do not fit 64).
 template <int FC, int P, int G>
 constexpr int das_waves_per_simd() {
     constexpr int bytes = G * 2 * FC * P * 16;
     constexpr int wgs = (160 * 1024) / bytes;
-    constexpr int cap = !stage_pairs(FC) ? 8 : (FC >= 32 ? 3 : 4);
+    constexpr int cap = !stage_pairs(FC) ? (FC >= 8 ? 6 : 8) : (FC >= 32 ? 3 : 4);
     return (wgs * G) < 1 ? 1 : ((wgs * G) > cap ? cap : wgs * G);
 }
 
@@ -529,7 +530,7 @@ static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, v
 //    piece (a split window costs a whole extra multiply-accumulate pass), and at least 65 rows for
 //    8- and 16-frame chunks (33-row variants measured 5-17% slower there);
 //  - few tiles (fewer than two per CU at FC = 32) favour 16-frame chunks; 5-8 frames take 8-frame chunks
-//    unless the grid is large (then 4-frame chunks, which hold 8 waves per SIMD);
+//    (c3, 8 frames on 3456 tiles: 5.13 ms against 6.84 ms in 4-frame chunks);
 //  - with fewer workgroups than CUs (256), the frame chunk is halved until there are enough;
 //  - a launch should then hold about 6144 waves (FC <= 4) or 2560 waves (FC >= 8), or 8192 when tiles carry
 //    1024 or more (transmit, element) items on average (3D, many elements: a c3 slab of 576 tiles ran 2.09 ms
@@ -557,7 +558,7 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles, double items
     int fc;
     if (frames >= 32) fc = (n_tiles < 512) ? 16 : 32;
     else if (frames > 8) fc = 16;
-    else if (frames > 4) fc = (n_tiles <= 2048) ? 8 : 4;
+    else if (frames > 4) fc = 8;
     else fc = frames > 2 ? 4 : frames > 1 ? 2 : 1;
     if (const char* env = std::getenv("DAS_VARIANT")) {  // tuning override: "fc,pitch,groups"
         int f = 0, pp = 0, g = 0;
