@@ -107,6 +107,7 @@ def test_parity_c1_full():
     z = cfg["vox"][:, 2]
     deep = z > 1540.0 * (1024 + 1) / (2 * 30.4e6)  # round trip longer than the record plus one sample
     assert deep.any() and np.all(y[deep] == 0)
+    assert info["kernel"] == (1, 129, 4)  # the launch configuration bench.py times for c1
 
 
 def test_parity_c2_full_size_sampled():
@@ -116,6 +117,7 @@ def test_parity_c2_full_size_sampled():
     print("c2 nrmse dB", db, "peak dB", oracle.peak_err_db(ys, ref), info)
     assert db <= DB_BAR
     assert y.shape == (65536, 32) and np.isfinite(y).all()
+    assert info["kernel"] == (16, 65, 2)  # the launch configuration of the bench line
 
 
 def test_parity_c2_251_full_size_sampled():
@@ -135,6 +137,7 @@ def test_parity_c3_full_size_sampled():
     db = oracle.nrmse_db(ys, ref)
     print("c3 nrmse dB", db, info)
     assert db <= DB_BAR
+    assert info["kernel"] == (8, 65, 1)  # one unpaired 8-frame chunk per tile, as bench.py times c3
 
 
 # ---------------------------------------------------------- special cases
