@@ -266,6 +266,30 @@ def test_16bit_iq_parity_and_storage_error(kind):
     assert db <= (-65.0 if kind == "f16" else -45.0)
 
 
+@pytest.mark.parametrize("kind", ["f16", "bf16"])
+def test_16bit_iq_parity_c3_full_size_sampled(kind):
+    """c3 at full size with IQ stored as FP16 / BF16, in the variant the benchmark times, against the oracle on
+    the same quantised samples."""
+    cfg = make_config("c3", with_iq=False)
+    p = cfg["params"]
+    iq = random_iq((5, 1024, p["n_samples"], p["n_frames"]), seed=34)
+    op = oracle_params(cfg)
+    vox = cfg["vox"]
+    tx = tx_table(vox, cfg["angles"], op["c"])
+    y, info, iq_t = gpu_das(iq, cfg["elem"], vox, tx, op, iq_dtype=kind)
+    del iq
+    q = iq_t.float().cpu().numpy()
+    del iq_t
+    iq_q = (q[..., 0] + 1j * q[..., 1]).astype(np.complex128)
+    del q
+    idx = np.sort(np.random.default_rng(35).choice(vox.shape[0], 96, replace=False))
+    ref_q = oracle.das(iq_q, cfg["elem"], vox[idx], tx[:, idx], **op)
+    db = oracle.nrmse_db(y[idx], ref_q)
+    print("c3", kind, info["kernel"], "nrmse dB on the quantised samples", db)
+    assert db <= DB_BAR
+    assert info["kernel"] == (8, 65, 1)
+
+
 def test_one_plan_on_two_streams_concurrently():
     """The plan is immutable: executing it on two streams at once gives the same bits as one at a time."""
     cfg = make_config("c2", with_iq=False, n_frames=8)
