@@ -42,6 +42,7 @@ WORKLOAD_CONFIG = {"c3_f1": ("c3", {"n_frames": 1}, None), "c3_v8": ("c3", {}, (
                    "c3_v4f4": ("c3", {"n_frames": 4}, (36, 60)), "c3_v2f2": ("c3", {"n_frames": 2}, (24, 72))}
 FLOP_PER_POINT = 16          # two complex multiply-accumulates per (voxel, element, transmit, frame)
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (256 CU x 2.4 GHz x 256 FLOP/clk)
+PEAK_HBM_GBPS = 8000.0       # MI355X published HBM3E bandwidth
 PAPER_PTS_PER_S = 258052096 / 0.23e-3   # RTX 5090, 251 x 251 rotating disk (context only)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "das_kernel_traffic.txt")
 
@@ -222,6 +223,21 @@ def scaling_sweep(axis, steps, warmup):
         del iq, out
 
 
+def hbm_report(T, E, S, F, V, info, ms, traffic):
+    """The HBM side of the roofline for one launch: compulsory bytes (IQ read once, output written once, the
+    transmit table and the voxel and element coordinates), their rate against the 8 TB/s peak, the measured HBM
+    bytes (PMC record) as a rate, and the kernel's on-chip gather rate (16 B of LDS operands per processed point
+    and frame)."""
+    compulsory = T * E * S * F * 8 + V * F * 8 + T * V * 4 + V * 12 + E * 12
+    sec = ms * 1e-3
+    rep = {"compulsory_bytes": compulsory, "compulsory_GBps": compulsory / sec / 1e9,
+           "peak_GBps": PEAK_HBM_GBPS, "frac": compulsory / sec / 1e9 / PEAK_HBM_GBPS,
+           "measured_bytes": traffic, "measured_GBps": None if traffic is None else traffic / sec / 1e9,
+           "gather_GBps": info["processed_triples"] * F * 16 / sec / 1e9,
+           "note": "the path is bound on chip (VALU, LDS), not by HBM: its intensity is far above the ridge"}
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +329,7 @@ def main():
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "das_kernel<fc=%d, pitch=%d, complex64, groups=%d>" % info["kernel"],
                      "work": "%d FLOP x active points (w > 0, inside the record) per launch" % FLOP_PER_POINT},
+        "hbm": hbm_report(T, E, S, F, V, info, ms, measured_traffic(args.workload)),
         "paper_context": {"points_per_s": PAPER_PTS_PER_S, "hardware": "NVIDIA GeForce RTX 5090",
                           "workload": "PyMUST rotating disk 251 x 251, 32 frames"},
     }

@@ -50,3 +50,15 @@ def test_iq16_range_report():
     assert r["max_abs_component"] == 70000.0 and not r["fits_fp16"]
     assert 0.0 < r["fp16_flushed_to_zero_fraction"] < 1.0
     assert r["bf16_subnormal_fraction"] > 0.0  # 1e-40 is below float32's normal range
+
+
+def test_hbm_report_compulsory_bytes():
+    """c2's compulsory traffic: IQ once (1 x 128 x 2048 x 32 complex64), output once (65536 x 32 complex64), the
+    transmit table (float32) and the voxel and element coordinates (3 float32 each)."""
+    info = {"processed_triples": 1000}
+    r = bench.hbm_report(1, 128, 2048, 32, 65536, info, 0.1, None)
+    assert r["compulsory_bytes"] == 67108864 + 16777216 + 262144 + 786432 + 1536
+    assert abs(r["compulsory_GBps"] - r["compulsory_bytes"] / 1e-4 / 1e9) < 1e-6
+    assert abs(r["frac"] - r["compulsory_GBps"] / 8000.0) < 1e-12
+    assert r["measured_GBps"] is None and r["gather_GBps"] == 1000 * 32 * 16 / 1e-4 / 1e9
+    assert bench.hbm_report(1, 128, 2048, 32, 65536, info, 0.1, 2e8)["measured_GBps"] == 2e8 / 1e-4 / 1e9
