@@ -208,6 +208,22 @@ int das_version(void);
  * a different order, so results may differ in the last bits). */
 int das_kernel_variants(int32_t *fc_pitch_groups, int32_t capacity);
 
+/* The variant das_plan_create picks, from the quantities it picks it by:
+ *   n_frames        F >= 1;
+ *   max_window      the largest per-tile sample window in rows (>= 0), as
+ *                   das_plan_info.max_window reports it;
+ *   n_tiles         workgroup tiles (>= 1);
+ *   items_per_tile  processed (slot, element, transmit) triples / voxels, i.e.
+ *                   the slot-weighted mean count of non-empty windows per tile
+ *                   (>= 0; das_plan_info.processed_triples / n_vox);
+ *   fc_pitch_groups host int32 [3]: receives (frames per workgroup, LDS pitch,
+ *                   element groups).
+ * The DAS_VARIANT override (above) applies here as at plan creation.
+ * Returns DAS_OK, DAS_EINVAL (NULL output, out-of-range argument) or
+ * DAS_ESHAPE (no compiled variant).  Host-only; no GPU call. */
+int das_choose_kernel_variant(int32_t n_frames, int32_t max_window, int64_t n_tiles, double items_per_tile,
+                              int32_t *fc_pitch_groups);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ DAS_IQ_C16BF = 2
 # Every symbol include/das.h declares.
 EXPORTED = ("das_plan_create", "das_execute", "das_execute_per_tx", "das_plan_destroy", "das_tx_plane_wave",
             "das_plan_query", "das_tile_order", "das_status_string", "das_last_error", "das_version",
-            "das_kernel_variants")
+            "das_kernel_variants", "das_choose_kernel_variant")
 
 # Every symbol include/das_learn.h declares.
 LEARN_EXPORTED = ("das_conv3d", "das_conv3d_wgrad", "das_conv3d_wgrad_work", "das_transpose_weights",
@@ -86,6 +86,8 @@ def load():
     lib.das_version.restype = ctypes.c_int
     lib.das_kernel_variants.argtypes = [vp, i32]
     lib.das_kernel_variants.restype = ctypes.c_int
+    lib.das_choose_kernel_variant.argtypes = [i32, i32, ctypes.c_int64, ctypes.c_double, vp]
+    lib.das_choose_kernel_variant.restype = ctypes.c_int
     _declare_learn(lib)
     _lib = lib
     return lib

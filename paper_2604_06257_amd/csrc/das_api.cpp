@@ -310,13 +310,27 @@ static hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 extern "C" {
 
-int das_version(void) { return (1 << 16) | 2; }
+int das_version(void) { return (1 << 16) | 3; }
 
 int das_kernel_variants(int32_t* fc_pitch_groups, int32_t capacity) {
     g_err.clear();
     if (capacity < 0) return fail(DAS_EINVAL, "capacity < 0");
     if (capacity > 0 && !fc_pitch_groups) return fail(DAS_EINVAL, "fc_pitch_groups is NULL");
     return das::list_variants(fc_pitch_groups, capacity);
+}
+
+int das_choose_kernel_variant(int32_t n_frames, int32_t max_window, int64_t n_tiles, double items_per_tile,
+                              int32_t* fc_pitch_groups) {
+    g_err.clear();
+    if (!fc_pitch_groups) return fail(DAS_EINVAL, "fc_pitch_groups is NULL");
+    if (n_frames < 1 || max_window < 0 || n_tiles < 1 || !(items_per_tile >= 0.0))
+        return fail(DAS_EINVAL, "need n_frames >= 1, max_window >= 0, n_tiles >= 1, items_per_tile >= 0");
+    const das::Variant v = das::choose_variant(n_frames, max_window, n_tiles, items_per_tile);
+    if (v.fc == 0) return fail(DAS_ESHAPE, "no compiled variant for %d frames", (int)n_frames);
+    fc_pitch_groups[0] = v.fc;
+    fc_pitch_groups[1] = v.pitch;
+    fc_pitch_groups[2] = v.groups;
+    return DAS_OK;
 }
 
 const char* das_last_error(void) { return g_err.c_str(); }

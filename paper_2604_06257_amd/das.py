@@ -183,6 +183,14 @@ def kernel_variants():
     return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(n)]
 
 
+def choose_kernel_variant(n_frames, max_window, n_tiles, items_per_tile):
+    """The variant a plan with these figures gets (das_choose_kernel_variant): (fc, pitch, groups)."""
+    lib = _lib.load()
+    buf = (ctypes.c_int32 * 3)()
+    check(lib.das_choose_kernel_variant(int(n_frames), int(max_window), int(n_tiles), float(items_per_tile), buf))
+    return (buf[0], buf[1], buf[2])
+
+
 def beamform(iq, elem_xyz, vox_xyz, tx_arrival, params, out=None, stream=None):
     """One-shot convenience: plan, execute, destroy."""
     with Plan(params, elem_xyz, vox_xyz, tx_arrival, stream=stream) as plan:

@@ -53,6 +53,44 @@ def test_kernel_variants_list():
     assert lib.das_kernel_variants(short, -1) == _lib.DAS_EINVAL
 
 
+@pytest.mark.parametrize("figures,expected", [
+    ((32, 35, 256, 70.0), (16, 65, 2)),      # c2: 256 tiles, 16-frame chunks, two element groups
+    ((8, 43, 3456, 1838.0), (8, 65, 1)),     # c3: one unpaired 8-frame chunk per tile, one group fills the chip
+    ((1, 100, 64, 60.0), (1, 129, 4)),       # c1: 64 tiles, groups added up to 4, pitch holds the window
+    ((6, 43, 2000, 500.0), (8, 65, 1)),      # 5-8 frames always take 8-frame chunks
+    ((16, 35, 64, 70.0), (4, 65, 4)),        # few tiles: the chunk halves until 256 workgroups (64 x 4)
+    ((64, 35, 1024, 70.0), (32, 41, 3)),     # F >= 32 on many tiles: 32-frame chunks, short windows
+    ((64, 47, 1024, 70.0), (32, 49, 3)),
+    ((64, 60, 1024, 70.0), (32, 65, 2)),
+    ((1, 100, 3456, 3700.0), (1, 129, 1)),   # item-heavy tiles: an 8192-wave target reached with one group
+])
+def test_variant_rule(figures, expected, monkeypatch):
+    """das_choose_kernel_variant (host-only) gives the variants the plan rule documents, including the
+    launch configurations the benchmark times for c1, c2 and c3."""
+    monkeypatch.delenv("DAS_VARIANT", raising=False)
+    got = das.choose_kernel_variant(*figures)
+    assert got == expected
+    assert got in das.kernel_variants()
+
+
+def test_variant_rule_override_and_errors(monkeypatch):
+    monkeypatch.setenv("DAS_VARIANT", "8,65,2")
+    assert das.choose_kernel_variant(8, 43, 3456, 1838.0) == (8, 65, 2)
+    monkeypatch.setenv("DAS_VARIANT", "8,66,1")  # not compiled: ignored
+    assert das.choose_kernel_variant(8, 43, 3456, 1838.0) == (8, 65, 1)
+    monkeypatch.setenv("DAS_VARIANT", "32,65,2")  # more than twice the plan's 8 frames per workgroup: ignored
+    assert das.choose_kernel_variant(8, 43, 3456, 1838.0) == (8, 65, 1)
+    monkeypatch.delenv("DAS_VARIANT")
+    lib = _lib.load()
+    buf = (ctypes.c_int32 * 3)()
+    assert lib.das_choose_kernel_variant(8, 43, 3456, 1.0, None) == _lib.DAS_EINVAL
+    for bad in ((0, 43, 3456, 1.0), (8, -1, 3456, 1.0), (8, 43, 0, 1.0), (8, 43, 3456, float("nan")),
+                (8, 43, 3456, -1.0)):
+        assert lib.das_choose_kernel_variant(*bad, buf) == _lib.DAS_EINVAL, bad
+    with pytest.raises(ValueError):
+        das.choose_kernel_variant(0, 43, 3456, 1.0)
+
+
 def test_status_strings():
     lib = _lib.load()
     assert lib.das_status_string(0) == b"ok"
