@@ -140,6 +140,18 @@ def test_parity_c3_full_size_sampled():
     assert info["kernel"] == (8, 65, 1)  # one unpaired 8-frame chunk per tile, as bench.py times c3
 
 
+def test_parity_c2_grid_many_frames_sampled():
+    """The c2 grid with 200 frames: 13 chunks of 16 frames, the last one ragged (8 frames), at full grid size."""
+    cfg = make_config("c2", with_iq=False, n_frames=200)
+    p = cfg["params"]
+    iq = random_iq((1, 128, p["n_samples"], 200), seed=36)
+    y, ys, ref, info = _sampled_parity(cfg, 256, 37, iq=iq)
+    db = oracle.nrmse_db(ys, ref)
+    print("c2 grid, 200 frames: nrmse dB", db, info["kernel"])
+    assert db <= DB_BAR
+    assert info["kernel"][0] == 16 and y.shape == (65536, 200) and np.isfinite(y).all()
+
+
 # ---------------------------------------------------------- special cases
 def test_zero_in_zero_out_bitwise():
     cfg = make_config("c2", with_iq=False, n_frames=4)
