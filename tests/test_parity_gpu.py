@@ -152,6 +152,25 @@ def test_parity_c2_grid_many_frames_sampled():
     assert info["kernel"][0] == 16 and y.shape == (65536, 200) and np.isfinite(y).all()
 
 
+@pytest.mark.parametrize("n_side,E,F,kernel", [(256, 8192, 8, (8, 65, 4)), (2510, 128, 8, (8, 65, 1))])
+def test_parity_sweep_extremes_sampled(n_side, E, F, kernel):
+    """The largest points of the element and voxel sweeps (8192 elements over the 38.4 mm aperture; a 2510 x 2510
+    grid, 6.3 M voxels) with 8 frames, against the oracle on sampled voxels."""
+    c, fc = 1540.0, 5e6
+    p = dict(c=c, fs=4 * fc, fd=fc, t0=0.0, f_number=1.0, tukey_alpha=0.5)
+    vox = grid_2d(np.linspace(-12.8e-3, 12.8e-3, n_side), np.linspace(10e-3, 35.5e-3, n_side))
+    elem = linear_array(E, 38.4e-3 / E)
+    tx = tx_table(vox, np.zeros((1, 2)), c)
+    iq = random_iq((1, E, 2048, F), seed=38)
+    y, info, _ = gpu_das(iq, elem, vox, tx, p)
+    idx = np.sort(np.random.default_rng(39).choice(vox.shape[0], 128, replace=False))
+    ref = oracle.das(iq, elem, vox[idx], tx[:, idx], **p)
+    db = oracle.nrmse_db(y[idx], ref)
+    print("sweep extreme", n_side, E, F, "nrmse dB", db, info["kernel"])
+    assert db <= DB_BAR
+    assert info["kernel"] == kernel and np.isfinite(y).all()
+
+
 # ---------------------------------------------------------- special cases
 def test_zero_in_zero_out_bitwise():
     cfg = make_config("c2", with_iq=False, n_frames=4)
