@@ -459,7 +459,9 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
         const int rows = var.pitch - 1;
         std::vector<int32_t> win((size_t)2 * tl.n_tiles * T * E);
         if (!win.empty() &&
-            (e = hipMemcpy(win.data(), d.windows, win.size() * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+            ((e = hipMemcpyAsync(win.data(), d.windows, win.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+                 hipSuccess ||
+             (e = hipStreamSynchronize(s)) != hipSuccess))
             goto hip_fail;
         std::vector<int4> items;
         std::vector<int32_t> off((size_t)tl.n_tiles + 1, 0);

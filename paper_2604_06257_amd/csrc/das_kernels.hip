@@ -193,6 +193,8 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     constexpr int NFG = FC / FPT;                                      // frame groups per row
     constexpr int RPT = (kRows * NFG + kSlots - 1) / kSlots;           // rows per fill thread
     using Raw = typename RawT<FPT * kEB>::type;
+    // the fill threads' runs of RPT rows cover every window row of every frame group
+    static_assert(((kRows + RPT - 1) / RPT) * NFG <= kSlots, "fill threads do not cover the stage");
     extern __shared__ float4 lds[];  // [G][2][FC][P]
     const das_kparams& kp = p.kp;
     // workgroup -> (tile, frame chunk): all chunks of the heaviest tiles are dispatched first
@@ -298,6 +300,10 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
         if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
+                // when RPT does not divide the window rows, the last fill thread's run passes row kRows - 1:
+                // rows kRows and up belong to the pad or the next frame slot, which no lane reads but another
+                // thread may be writing, so they are not stored
+                if (kRows % RPT != 0 && row0 + j >= kRows) break;
 #pragma unroll
                 for (int q = 0; q < FPT; ++q) {
                     const float2 a = decode<DT>(raw[j], q), b = decode<DT>(raw[j + 1], q);

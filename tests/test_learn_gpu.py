@@ -293,8 +293,64 @@ def test_unet_forward_and_gradients_match_oracle(dims, chans):
             assert c0 >= 0.99, (name, what, c0)
 
 
+@pytest.mark.parametrize("dims", [(48, 48, 48), (40, 48, 64)])
+def test_unet_gradients_match_independent_bf16_oracle(dims):
+    """The network's weight and bias gradients against the FP64 oracle network run from the inputs alone (no
+    tensor taken from the GPU).  The oracle stores its activations and propagated gradients rounded to bfloat16
+    at the points where the kernels store theirs, so both compute the same function.
+
+    Bound: cosine >= 0.999 and relative L2 <= 2e-2 for every layer.  A network that stores bfloat16 tensors
+    is sensitive to the accumulation precision: where an FP32 and an FP64 sum round to neighbouring bfloat16
+    values the difference propagates, and a ReLU decision can change.  The same oracle run with FP32
+    accumulation (the yardstick computed here) differs from the FP64 one by up to 1.9e-2 relL2 at 48^3 and
+    3.3e-2 at 32^3 in the deepest layers, so relL2 <= 1e-2 end to end is below the floor that any FP32
+    implementation of this network meets (measured on the GPU test inputs: GPU 1.16e-2 and yardstick 1.07e-2
+    at 48^3, 8.9e-3 and 7.1e-3 at 40 x 48 x 64).  The GPU's worst layer must stay within twice the
+    yardstick's worst layer (and 1e-2), and every layer within 2e-2.  Given the same stored forward tensors
+    (the test above) the bound is relL2 <= 1e-2."""
+    L = _learn()
+    D, H, W = dims
+    chans = (16, 32, 48, 64)
+    r = np.random.default_rng(51)
+    net = L.UNet(dims, cin=8, chans=chans, cout=16)
+    net.init_params(seed=7, out_scale=1.0)
+    p = {k: (w, r.standard_normal(b.shape).astype(np.float32) * 0.05) for k, (w, b) in net.get_params().items()}
+    net.set_params(p)
+    params = {k: (bf16_round(w), b.astype(np.float32).astype(np.float64)) for k, (w, b) in p.items()}
+    x = bf16_round(r.standard_normal((D, H, W, 8)))
+    base = r.standard_normal((D, H, W, 2)).astype(np.float32)
+    tgt = r.standard_normal((D, H, W, 2)).astype(np.float32)
+    got = host(net.forward(to_dev_bf16(x))).reshape(D, H, W, 16)
+    net.loss(torch.as_tensor(base.reshape(-1, 2), device=DEV), torch.as_tensor(tgt.reshape(-1, 2), device=DEV))
+    net.backward(to_dev_bf16(x))
+    grads = net.get_grads()
+    ref_net, cache = U.forward(params, x, store=bf16_round)
+    assert cosine(got, ref_net) > 0.9999 and rel_l2(got, ref_net) < 1e-2
+    _, gnet = U.loss_and_grad_net(ref_net, base.astype(np.float64), tgt.astype(np.float64))
+    ref = U.backward(params, cache, gnet, store=bf16_round)
+    # yardstick: the same definition accumulated in float32
+    st32 = lambda a: bf16_round(a).astype(np.float32)  # noqa: E731
+    p32 = {k: (w.astype(np.float32), b.astype(np.float32)) for k, (w, b) in params.items()}
+    net32, cache32 = U.forward(p32, x.astype(np.float32), store=st32)
+    _, gnet32 = U.loss_and_grad_net(net32.astype(np.float64), base.astype(np.float64), tgt.astype(np.float64))
+    ref32 = U.backward(p32, cache32, gnet32.astype(np.float32), store=st32)
+    worst, worst32 = (1.0, 0.0), 0.0
+    for name in ref:
+        for i, what in enumerate(("w", "b")):
+            g = grads[name][i].astype(np.float64).reshape(ref[name][i].shape)
+            c, e = cosine(g, ref[name][i]), rel_l2(g, ref[name][i])
+            e32 = rel_l2(ref32[name][i].astype(np.float64), ref[name][i])
+            worst, worst32 = (min(worst[0], c), max(worst[1], e)), max(worst32, e32)
+            print("%s.%s vs independent bf16-store FP64 oracle: GPU cos %.6f relL2 %.2e | FP32 yardstick relL2 %.2e"
+                  % (name, what, c, e, e32))
+            assert c >= 0.999 and e <= 2e-2, (name, what, c, e)
+    print("worst over layers: GPU cos %.6f relL2 %.2e | FP32 yardstick relL2 %.2e" % (worst + (worst32,)))
+    assert worst[1] <= 2.0 * max(5e-3, worst32)
+
+
 def test_unet_training_reduces_loss_deterministically():
-    """Adam on one fixed batch: the loss falls, and two identical runs give identical weights."""
+    """Adam on one fixed batch: within 100 steps the loss falls below 0.6 of its first value, and two identical
+    runs give identical weights."""
     L = _learn()
     dims = (16, 16, 16)
     r = np.random.default_rng(31)
@@ -309,10 +365,11 @@ def test_unet_training_reduces_loss_deterministically():
         net = L.UNet(dims)
         net.init_params(seed=3)
         losses = []
-        for _ in range(60):
+        for _ in range(100):
             parts = net.train_step(x, base, tgt, lr=2e-3)
             losses.append(float(parts.sum()) / (2 * net.V[0]))
         torch.cuda.synchronize()
-        assert losses[-1] < 0.7 * losses[0], losses
+        print("loss ratio after 60 / 100 steps: %.3f / %.3f" % (losses[59] / losses[0], losses[-1] / losses[0]))
+        assert losses[-1] < 0.6 * losses[0], losses
         finals.append(net.master.clone())
     assert torch.equal(finals[0], finals[1])
