@@ -188,7 +188,7 @@ const char *das_status_string(int status);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *das_last_error(void);
 
-/* ABI version: (major << 16) | minor (this header: 1.3). */
+/* ABI version: (major << 16) | minor (this header: 1.4; 1.4 added das_power_doppler_noalloc to das_post.h). */
 int das_version(void);
 
 /* The compiled beamforming kernel variants, as (frames per workgroup, LDS row

@@ -42,11 +42,25 @@ int64_t das_bmode_work(int64_t V, int F);
  * singular value (eigenvectors of C^H C from a float64 Jacobi solver) and
  * k = n_clutter (0 <= k <= F; k = 0 gives the frame energy).  float32 [V]
  * output, float64 arithmetic.  work holds das_power_doppler_work(V, F)
- * doubles (its contents on return are internal).  DAS_ESHAPE unless V >= 1
+ * doubles, 16-byte aligned (its contents on return are internal).  DAS_ESHAPE unless V >= 1
  * and 1 <= F <= 32; DAS_EINVAL unless 0 <= n_clutter <= F. */
 int das_power_doppler(const void *y, int64_t V, int F, int n_clutter, float *pd, double *work, int64_t work_doubles,
                       void *stream);
 int64_t das_power_doppler_work(int64_t V, int F);
+
+/* Power Doppler as das_power_doppler, for callers that cannot allocate device
+ * memory or pass a work buffer (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): its work lives in a fixed 8.03 MiB
+ * device array of the library, one per GPU, kept until the process ends.  The
+ * call allocates nothing and takes the same arguments minus the work buffer.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (concurrent streams or threads) race and must be serialised by the caller.
+ * Up to 16 frames the result is bitwise that of das_power_doppler; with 17-32
+ * frames the Gram matrix is summed over fewer, larger voxel chunks (float64
+ * partial sums in another grouping).  The voxel count is not limited (chunks
+ * grow with V).  DAS_ESHAPE unless V >= 1 and 1 <= F <= 32; DAS_EINVAL unless
+ * 0 <= n_clutter <= F; DAS_EHIP if the array's address cannot be obtained. */
+int das_power_doppler_noalloc(const void *y, int64_t V, int F, int n_clutter, float *pd, void *stream);
 
 /* Thread-local message of the last failing call of this header ("" if none). */
 const char *das_post_last_error(void);

@@ -34,7 +34,8 @@ LEARN_EXPORTED = ("das_conv3d", "das_conv3d_wgrad", "das_conv3d_wgrad_work", "da
                   "das_compound_rescale", "das_compound_output", "das_learn_last_error")
 
 # Every symbol include/das_post.h declares.
-POST_EXPORTED = ("das_bmode", "das_bmode_work", "das_power_doppler", "das_power_doppler_work", "das_post_last_error")
+POST_EXPORTED = ("das_bmode", "das_bmode_work", "das_power_doppler", "das_power_doppler_work",
+                 "das_power_doppler_noalloc", "das_post_last_error")
 
 
 class DasParams(ctypes.Structure):
@@ -120,6 +121,7 @@ def _declare_learn(lib):
         fn.restype = ctypes.c_int
     post = {"das_bmode": [vp, i64, i32, f32, vp, vp, i64, vp], "das_bmode_work": [i64, i32],
             "das_power_doppler": [vp, i64, i32, i32, vp, vp, i64, vp], "das_power_doppler_work": [i64, i32],
+            "das_power_doppler_noalloc": [vp, i64, i32, i32, vp, vp],
             "das_post_last_error": []}
     for name, args in post.items():
         fn = getattr(lib, name)

@@ -310,7 +310,7 @@ static hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
 
 extern "C" {
 
-int das_version(void) { return (1 << 16) | 3; }
+int das_version(void) { return (1 << 16) | 4; }
 
 int das_kernel_variants(int32_t* fc_pitch_groups, int32_t capacity) {
     g_err.clear();

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "das_post.h"
 
@@ -310,10 +311,59 @@ int pfail(int st, const char* msg) {
 int post_launch_status(const char* what) {
     return hipGetLastError() == hipSuccess ? DAS_OK : pfail(DAS_EHIP, what);
 }
-// voxels per Gram partial block: enough blocks (up to 2048) to fill the chip, at least one 64-voxel tile each
-int64_t gram_chunk(int64_t V) {
-    const int64_t c = (V + 2047) / 2048;
+// voxels per Gram partial block: at most max_blocks blocks (2048 fill the chip), at least one 64-voxel tile each
+int64_t gram_chunk(int64_t V, int64_t max_blocks = 2048) {
+    const int64_t c = (V + max_blocks - 1) / max_blocks;
     return c < 64 ? 64 : c;
+}
+
+// Work layout of Power Doppler in double2 units: nb partial Gram matrices, their sum, the eigenvectors, then the
+// F eigenvalues (doubles, rounded up to whole double2).
+int64_t pd_work2(int64_t nb, int F) { return nb * F * F + 2 * (int64_t)F * F + (F + 1) / 2; }
+
+// Allocation-free Power Doppler: its work lives in this fixed device array (one per GPU, kept until the process
+// ends).  Size: the work of 2048 partial blocks at 16 frames, so that up to 16 frames the voxel chunking is the
+// same as with a caller's buffer; 17-32 frames use fewer, larger chunks.
+constexpr int64_t kScratch2 = 2048 * 16 * 16 + 2 * 32 * 32 + 16;  // double2 entries (8.03 MiB)
+static __device__ __align__(256) double2 scratch[kScratch2];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device, looked up once per device.  The array's host-side
+// name is not a device address; only this pointer is passed to kernels.
+int scratch_on_current_device(double2** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return pfail(DAS_EHIP, "power_doppler_noalloc: no current HIP device");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+            return pfail(DAS_EHIP, "power_doppler_noalloc: hipGetSymbolAddress(scratch) failed");
+        g_scratch_ptr[dev] = static_cast<double2*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return DAS_OK;
+}
+
+// Power Doppler on a work area of work2 double2 entries with at most max_blocks Gram partial blocks.
+int power_doppler_impl(const void* y, int64_t V, int F, int n_clutter, float* pd, double2* work, int64_t max_blocks,
+                       hipStream_t s) {
+    const float2* yy = reinterpret_cast<const float2*>(y);
+    const int64_t chunk = gram_chunk(V, max_blocks);
+    const int nb = (int)((V + chunk - 1) / chunk);
+    double2* part = work;
+    double2* gram = part + (int64_t)nb * F * F;
+    double2* vec = gram + (int64_t)F * F;
+    double* eval = reinterpret_cast<double*>(vec + (int64_t)F * F);
+    hipLaunchKernelGGL(post::gram_partial_kernel, dim3(nb), dim3(256), 0, s, yy, V, F, chunk, part);
+    hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, gram);
+    hipLaunchKernelGGL(post::jacobi_kernel<256>, dim3(1), dim3(256), 0, s, gram, 1, F, vec, eval, 40);
+    hipLaunchKernelGGL(post::pd_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, yy, V, F, n_clutter, vec,
+                       pd);
+    return post_launch_status("power_doppler launch failed");
 }
 }  // namespace
 
@@ -349,7 +399,7 @@ int das_bmode(const void* y, int64_t V, int F, float dynamic_range_db, float* ou
 int64_t das_power_doppler_work(int64_t V, int F) {
     if (V < 1 || F < 1) return 0;
     const int64_t nb = (V + gram_chunk(V) - 1) / gram_chunk(V);
-    return 2 * (nb * F * F + 2 * (int64_t)F * F) + F;  // partial Gram matrices, the sum, eigenvectors; eigenvalues
+    return 2 * pd_work2(nb, F);  // partial Gram matrices, the sum, eigenvectors; eigenvalues
 }
 
 int das_power_doppler(const void* y, int64_t V, int F, int n_clutter, float* pd, double* work, int64_t work_doubles,
@@ -358,20 +408,25 @@ int das_power_doppler(const void* y, int64_t V, int F, int n_clutter, float* pd,
     if (V < 1 || F < 1 || F > post::kMaxF) return pfail(DAS_ESHAPE, "power_doppler: need V >= 1 and 1 <= F <= 32");
     if (n_clutter < 0 || n_clutter > F) return pfail(DAS_EINVAL, "power_doppler: need 0 <= n_clutter <= F");
     if (work_doubles < das_power_doppler_work(V, F)) return pfail(DAS_ESHAPE, "power_doppler: work buffer too small");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const float2* yy = reinterpret_cast<const float2*>(y);
-    const int64_t chunk = gram_chunk(V);
-    const int nb = (int)((V + chunk - 1) / chunk);
-    double2* part = reinterpret_cast<double2*>(work);
-    double2* gram = part + (int64_t)nb * F * F;
-    double2* vec = gram + (int64_t)F * F;
-    double* eval = reinterpret_cast<double*>(vec + (int64_t)F * F);
-    hipLaunchKernelGGL(post::gram_partial_kernel, dim3(nb), dim3(256), 0, s, yy, V, F, chunk, part);
-    hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, gram);
-    hipLaunchKernelGGL(post::jacobi_kernel<256>, dim3(1), dim3(256), 0, s, gram, 1, F, vec, eval, 40);
-    hipLaunchKernelGGL(post::pd_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, yy, V, F, n_clutter, vec,
-                       pd);
-    return post_launch_status("power_doppler launch failed");
+    if (reinterpret_cast<uintptr_t>(work) % 16 != 0) return pfail(DAS_EALIGN, "power_doppler: work must be 16-byte aligned");
+    return power_doppler_impl(y, V, F, n_clutter, pd, reinterpret_cast<double2*>(work), 2048,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+int das_power_doppler_noalloc(const void* y, int64_t V, int F, int n_clutter, float* pd, void* stream) {
+    if (!y || !pd) return pfail(DAS_EINVAL, "power_doppler_noalloc: null pointer");
+    if (V < 1 || F < 1 || F > post::kMaxF)
+        return pfail(DAS_ESHAPE, "power_doppler_noalloc: need V >= 1 and 1 <= F <= 32");
+    if (n_clutter < 0 || n_clutter > F) return pfail(DAS_EINVAL, "power_doppler_noalloc: need 0 <= n_clutter <= F");
+    // the most Gram partial blocks the scratch array holds at F frames (F <= 32 always leaves room for 500)
+    const int64_t fit = (kScratch2 - pd_work2(0, F)) / ((int64_t)F * F);
+    const int64_t max_blocks = fit < 2048 ? fit : 2048;
+    if (pd_work2((V + gram_chunk(V, max_blocks) - 1) / gram_chunk(V, max_blocks), F) > kScratch2)
+        return pfail(DAS_ESHAPE, "power_doppler_noalloc: work exceeds the 8 MiB scratch array");
+    double2* work = nullptr;
+    const int st = scratch_on_current_device(&work);
+    if (st != DAS_OK) return st;
+    return power_doppler_impl(y, V, F, n_clutter, pd, work, max_blocks, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

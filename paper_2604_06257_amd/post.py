@@ -47,3 +47,17 @@ def power_doppler(y, n_clutter, out=None, stream=None):
                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()), work.numel(),
                                      _stream(stream)), post=True)
     return out
+
+
+def power_doppler_noalloc(y, n_clutter, out, stream=None):
+    """Power Doppler into the caller's float32 [V] ``out`` with the library's fixed scratch array (no work buffer;
+    calls that overlap on one GPU race)."""
+    _check_y(y)
+    V, F = y.shape
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float32 or out.shape != (V,) \
+            or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [V] device tensor")
+    lib = _lib.load()
+    _lib.check(lib.das_power_doppler_noalloc(ctypes.c_void_p(y.data_ptr()), V, F, int(n_clutter),
+                                             ctypes.c_void_p(out.data_ptr()), _stream(stream)), post=True)
+    return out

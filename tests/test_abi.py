@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib.load()
     for name in declared_functions():
         assert hasattr(lib, name), name
-    assert lib.das_version() == (1 << 16) | 3  # the version include/das.h documents
+    assert lib.das_version() == (1 << 16) | 4  # the version include/das.h documents
 
 
 def test_kernel_variants_list():
