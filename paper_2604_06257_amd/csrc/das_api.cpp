@@ -294,7 +294,7 @@ static bool plan_live(const das_plan* plan) {
 }
 
 static void free_dev(das::PlanDev& d) {
-    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elem, d.windows, d.items, d.item_off, d.wg_unit};
+    void* ptrs[] = {d.vx, d.vy, d.vz, d.tx, d.slot_vox, d.elemd, d.windows, d.items, d.item_off, d.wg_unit};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = das::PlanDev();
@@ -419,19 +419,27 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
     d.n_vox = p->n_vox;
     kp.n_tiles = (int32_t)tl.n_tiles;
     kp.use_apod = p->f_number > 0 ? 1 : 0;
-    kp.inv_c = 1.0 / p->sound_speed;
+    kp.fs_c = p->fs / p->sound_speed;
+    kp.fd_c = p->f_demod / p->sound_speed;
     kp.fs = p->fs;
     kp.fd = p->f_demod;
-    kp.t0 = p->t0;
+    kp.t0fs = p->t0 * p->fs;
     kp.two_fnum = (float)(2.0 * p->f_number);
     kp.alpha = (float)p->tukey_alpha;
     kp.inv_2alpha = p->tukey_alpha > 0 ? (float)(0.5 / p->tukey_alpha) : 0.0f;
+    kp.edge_2alpha = p->tukey_alpha > 0 ? (float)((1.0 - p->tukey_alpha) * 0.5 / p->tukey_alpha) : 0.0f;
+    // elements in one depth plane (linear and matrix arrays): the depth terms are per voxel
+    kp.planar = 1;
+    for (int64_t k = 1; k < E; ++k)
+        if (elem[3 * k + 2] != elem[2]) kp.planar = 0;
+    kp.z0 = kp.planar ? (double)elem[2] : 0.0;
 
+    const std::vector<double> elemd(elem.begin(), elem.end());
     unsigned long long* counts = nullptr;
     unsigned long long hc[3] = {0, 0, 0};
     if ((e = upload(&d.vx, vx, s)) != hipSuccess || (e = upload(&d.vy, vy, s)) != hipSuccess ||
         (e = upload(&d.vz, vz, s)) != hipSuccess || (e = upload(&d.tx, txs, s)) != hipSuccess ||
-        (e = upload(&d.slot_vox, tl.slot_to_vox, s)) != hipSuccess || (e = upload(&d.elem, elem, s)) != hipSuccess)
+        (e = upload(&d.slot_vox, tl.slot_to_vox, s)) != hipSuccess || (e = upload(&d.elemd, elemd, s)) != hipSuccess)
         goto hip_fail;
     if ((e = hipMalloc((void**)&d.windows, std::max<int64_t>(1, 2 * tl.n_tiles * T * E) * sizeof(int32_t))) !=
         hipSuccess)

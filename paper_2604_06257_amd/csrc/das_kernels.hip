@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kSlots) void window_kernel(PlanDev p, unsigned long
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t slot = (int64_t)tile * kSlots + threadIdx.x;
     const bool valid = p.slot_vox[slot] >= 0;
-    const float vx = p.vx[slot], vy = p.vy[slot], vz = p.vz[slot];
+    const das_lane vl = das_lane_setup(p.vx[slot], p.vy[slot], p.vz[slot], kp);
     int n_valid = valid ? 1 : 0;
     for (int o = 32; o > 0; o >>= 1) n_valid += __shfl_xor(n_valid, o);
     __shared__ int s_valid[kWaves];
@@ -95,10 +96,10 @@ __global__ __launch_bounds__(kSlots) void window_kernel(PlanDev p, unsigned long
     unsigned long long active_sum = 0, processed_sum = 0;
     int max_win = 0;
     for (int e = 0; e < kp.E; ++e) {
-        const das_rx rx = das_rx_setup(vx, vy, vz, p.elem[3 * e], p.elem[3 * e + 1], p.elem[3 * e + 2], kp);
+        const das_rx rx = das_rx_setup(vl, p.elemd[3 * e], p.elemd[3 * e + 1], p.elemd[3 * e + 2], kp);
         for (int t = 0; t < kp.T; ++t) {
-            const das_coef c = das_tx_setup(rx, p.tx[(int64_t)t * kp.n_slots + slot], kp);
-            const bool act = valid && c.active;
+            const das_coef c = das_tx_setup(rx, das_tx_const(p.tx[(int64_t)t * kp.n_slots + slot], kp), kp);
+            const bool act = valid && das_active(rx, c, kp);
             int lo = act ? c.i0 : INT_MAX, hi = act ? c.i0 : INT_MIN, cnt = act ? 1 : 0;
             for (int o = 32; o > 0; o >>= 1) {
                 lo = min(lo, __shfl_xor(lo, o));
@@ -207,7 +208,7 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     const int gt = threadIdx.x % kSlots;  // slot within the tile
     const int64_t slot = (int64_t)tile * kSlots + gt;
     const int vox = p.slot_vox[slot];
-    const float vx = p.vx[slot], vy = p.vy[slot], vz = p.vz[slot];
+    const das_lane L = das_lane_setup(p.vx[slot], p.vy[slot], p.vz[slot], kp);
     float4* buf0 = lds + grp * 2 * kBuf;
     float4* buf1 = buf0 + kBuf;
     const int fgrp = gt % NFG, row0 = (gt / NFG) * RPT;
@@ -268,12 +269,14 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     // Stage rows 0 .. a.w - 1 are item a's window; item b's window starts at row bb(a) = a.w rounded up to a
     // multiple of RPT, so the RPT rows of a fill thread (and the sample after them) come from one record.
     auto bbase = [&](const int4& ia) { return (ia.w + RPT - 1) / RPT * RPT; };
-    auto load_item = [&](int k, Raw (&raw)[RPT + 1], float& txa, float& txb, int4& ia, int4& ib) {
+    auto load_item = [&](int k, Raw (&raw)[RPT + 1], float& txa, float& txb, int4& ia, int4& ib, auto one_tx) {
         ia = items[kIS * k];
         // without stage pairing the second item is a constant empty one and its code folds away
         ib = stage_pairs(FC) ? items[kIS * k + 1] : make_int4(0, 0, 0, 0);
-        txa = p.tx[(int64_t)ia.x * kp.n_slots + slot];
-        txb = ib.w > 0 ? p.tx[(int64_t)ib.x * kp.n_slots + slot] : 0.0f;
+        if constexpr (decltype(one_tx)::value == 0) {  // with one transmit its time is a per-lane constant
+            txa = p.tx[(int64_t)ia.x * kp.n_slots + slot];
+            txb = ib.w > 0 ? p.tx[(int64_t)ib.x * kp.n_slots + slot] : 0.0f;
+        }
         const int bb = bbase(ia);
         const bool in_b = ib.w > 0 && row0 >= bb;
         if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
@@ -312,19 +315,45 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
             }
         }
     };
-    // Coefficients of an item for this lane; lanes outside the aperture, the
-    // record or the item's window get zero weights and row 0 (so the MAC runs
-    // without branches and adds exact zeros).  base = the item's first stage row.
-    int last_e = -1;
+    // Coefficients of an item for this lane; lanes whose sample row is outside the item's window get zero
+    // weights and row 0 (so the MAC runs without branches and adds exact zeros).  A row inside the window is
+    // inside the record (windows span the rows of active lanes only); lanes outside the aperture carry w = 0;
+    // empty slots compute a valid voxel's sums that are never stored.  base = the item's first stage row.
+    // The receive part is kept while consecutive items share the element, the transmit part while they share
+    // the transmit (all items, when T = 1).
+    //
+    // With one transmit every item starts a new element (or continues a split window), so the coefficients
+    // are formed without branches from the item alone: the compiler then interleaves the next stage's FP64
+    // set-up chain with the current stage's multiply-accumulate, which hides both the chain's latency and the
+    // LDS reads'.  With several transmits the receive part is cached across the transmits of an element.
+    int last_e = -1, last_t = -1;
     das_rx rx;
-    auto coef_item = [&](const int4& it, float txv, bool live, int base) {
-        if (it.y != last_e) {
-            rx = das_rx_setup(vx, vy, vz, p.elem[3 * it.y], p.elem[3 * it.y + 1], p.elem[3 * it.y + 2], kp);
-            last_e = it.y;
+    das_txc tc;
+    const das_txc tc0 = das_tx_const(p.tx[slot], kp);  // transmit 0
+    // one_tx: a std::integral_constant<int, 0 | 1 | 2>: 0 = several transmits (cached receive part), 1 = one
+    // transmit and a planar array, 2 = one transmit and elements at several depths.
+    auto coef_item = [&](const int4& it, float txv, bool live, int base, auto one_tx) {
+        das_coef c;
+        if constexpr (decltype(one_tx)::value != 0) {
+            const double* e = p.elemd + 3 * it.y;
+            c = das_tx_setup(das_rx_setup_t<decltype(one_tx)::value == 1>(L, e[0], e[1], e[2], kp), tc0, kp);
+        } else {
+            // marked unlikely (it is taken once per element, every T-th item), so that the compiler keeps
+            // the branch rather than forming the receive part for every item
+            if (__builtin_expect(it.y != last_e, 0)) {
+                const double* e = p.elemd + 3 * it.y;
+                rx = das_rx_setup(L, e[0], e[1], e[2], kp);
+                last_e = it.y;
+            }
+            if (it.x != last_t) {
+                tc = das_tx_const(txv, kp);
+                last_t = it.x;
+            }
+            c = das_tx_setup(rx, tc, kp);
         }
-        das_coef c = das_tx_setup(rx, txv, kp);
-        const bool use = live && (vox >= 0) && c.active && c.i0 >= it.z && c.i0 < it.z + it.w;
-        c.row = use ? c.i0 - it.z + base : 0;
+        const unsigned d = (unsigned)c.i0 - (unsigned)it.z;
+        const bool use = live && d < (unsigned)it.w;
+        c.row = use ? (int)d + base : 0;
         c.t = it.x;
         // beta stays: with zero weights the lane adds exact zeros whatever it interpolates
         c.cr = use ? c.cr : 0.0f;
@@ -362,54 +391,66 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     // coefficients are zero) multiplies zeros, never stale or unset LDS.
     for (int i = gt; i < 2 * kBuf; i += kSlots) buf0[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     __syncthreads();
-    Raw ra[RPT + 1], rb[RPT + 1];
-    float txa0 = 0.0f, txa1 = 0.0f, txb0 = 0.0f, txb1 = 0.0f;
-    const int4 z4 = make_int4(0, 0, 0, 0);
-    int4 ia0 = z4, ia1 = z4, ib0 = z4, ib1 = z4;  // items (first, second) of pipeline slots a and b
-    if (grp < nitems) load_item(grp, ra, txa0, txa1, ia0, ia1);
-    if (grp + G < nitems) load_item(grp + G, rb, txb0, txb1, ib0, ib1);
-    // the second item's coefficients only when the stage has one (a wave-uniform branch; an empty item
-    // must not evict the cached receive geometry)
-    das_coef none;
-    none.i0 = 0;
-    none.row = 0;
-    none.beta = none.cr = none.ci = 0.0f;
-    none.active = false;
-    das_coef c0 = coef_item(ia0, txa0, grp < nitems, 0);
-    das_coef c1 = (grp < nitems && ia1.w > 0) ? coef_item(ia1, txa1, true, bbase(ia0)) : none;
-    bool two = grp < nitems && ia1.w > 0;
-    for (int step = 0; step < nsteps; step += 2) {
-        {
-            const int k = step * G + grp;
-            if (k < nitems) store_item(ia0, ia1, ra, buf0);
-            __syncthreads();
-            if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa0, txa1, ia0, ia1);
-            const bool live = k + G < nitems;
-            const das_coef n0 = coef_item(ib0, txb0, live, 0);  // stage k + G
-            const bool ntwo = live && ib1.w > 0;
-            const das_coef n1 = ntwo ? coef_item(ib1, txb1, true, bbase(ib0)) : none;
-            mac_item(c0, buf0);
-            if (two) mac_item(c1, buf0);
-            c0 = n0;
-            c1 = n1;
-            two = ntwo;
+    auto pipeline = [&](auto one_tx) {
+        constexpr bool kOne = decltype(one_tx)::value != 0;
+        Raw ra[RPT + 1], rb[RPT + 1];
+        float txa0 = 0.0f, txa1 = 0.0f, txb0 = 0.0f, txb1 = 0.0f;
+        const int4 z4 = make_int4(0, 0, 0, 0);
+        int4 ia0 = z4, ia1 = z4, ib0 = z4, ib1 = z4;  // items (first, second) of pipeline slots a and b
+        if (grp < nitems) load_item(grp, ra, txa0, txa1, ia0, ia1, one_tx);
+        if (grp + G < nitems) load_item(grp + G, rb, txb0, txb1, ib0, ib1, one_tx);
+        das_coef none;
+        none.i0 = 0;
+        none.row = 0;
+        none.t = 0;
+        none.beta = none.cr = none.ci = 0.0f;
+        // The second item's coefficients: with one transmit, always formed (zero weights when the stage has
+        // no second item), keeping the step one basic block; otherwise only when the stage has one (a
+        // wave-uniform branch: an empty item must not evict the cached receive geometry).
+        auto second = [&](const int4& i1, float tx1, bool has, int base) {
+            if constexpr (!stage_pairs(FC)) return none;
+            else if constexpr (kOne) return coef_item(i1, tx1, has, base, one_tx);
+            else return has ? coef_item(i1, tx1, true, base, one_tx) : none;
+        };
+        das_coef c0 = coef_item(ia0, txa0, grp < nitems, 0, one_tx);
+        bool two = grp < nitems && ia1.w > 0;
+        das_coef c1 = second(ia1, txa1, two, bbase(ia0));
+        for (int step = 0; step < nsteps; step += 2) {
+            {
+                const int k = step * G + grp;
+                if (k < nitems) store_item(ia0, ia1, ra, buf0);
+                __syncthreads();
+                if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa0, txa1, ia0, ia1, one_tx);
+                const bool live = k + G < nitems;
+                const das_coef n0 = coef_item(ib0, txb0, live, 0, one_tx);  // stage k + G
+                const bool ntwo = live && ib1.w > 0;
+                const das_coef n1 = second(ib1, txb1, ntwo, bbase(ib0));
+                mac_item(c0, buf0);
+                if (two) mac_item(c1, buf0);
+                c0 = n0;
+                c1 = n1;
+                two = ntwo;
+            }
+            if (step + 1 < nsteps) {
+                const int k = (step + 1) * G + grp;
+                if (k < nitems) store_item(ib0, ib1, rb, buf1);
+                __syncthreads();
+                if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb0, txb1, ib0, ib1, one_tx);
+                const bool live = k + G < nitems;
+                const das_coef n0 = coef_item(ia0, txa0, live, 0, one_tx);  // stage k + G
+                const bool ntwo = live && ia1.w > 0;
+                const das_coef n1 = second(ia1, txa1, ntwo, bbase(ia0));
+                mac_item(c0, buf1);
+                if (two) mac_item(c1, buf1);
+                c0 = n0;
+                c1 = n1;
+                two = ntwo;
+            }
         }
-        if (step + 1 < nsteps) {
-            const int k = (step + 1) * G + grp;
-            if (k < nitems) store_item(ib0, ib1, rb, buf1);
-            __syncthreads();
-            if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb0, txb1, ib0, ib1);
-            const bool live = k + G < nitems;
-            const das_coef n0 = coef_item(ia0, txa0, live, 0);  // stage k + G
-            const bool ntwo = live && ia1.w > 0;
-            const das_coef n1 = ntwo ? coef_item(ia1, txa1, true, bbase(ia0)) : none;
-            mac_item(c0, buf1);
-            if (two) mac_item(c1, buf1);
-            c0 = n0;
-            c1 = n1;
-            two = ntwo;
-        }
-    }
+    };
+    if (kp.T > 1) pipeline(std::integral_constant<int, 0>{});
+    else if (kp.planar) pipeline(std::integral_constant<int, 1>{});
+    else pipeline(std::integral_constant<int, 2>{});
     if (G > 1) {
         // Fixed-order reduction of the groups' partial sums through LDS:
         // ((g0 + g1) + g2) + ...
