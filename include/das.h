@@ -158,7 +158,9 @@ typedef struct das_plan_info {
                                   the points are not a lattice)                */
     int32_t max_window;        /* largest per-tile sample window (rows)        */
     int32_t kernel_fc;         /* kernel variant: frames per workgroup,        */
-    int32_t kernel_pitch;      /*   LDS row pitch (window rows + 1),           */
+    int32_t kernel_pitch;      /*   LDS row pitch (window rows + 1; 0 = the
+                                      direct kernel: 1-2 frames per workgroup,
+                                      samples read without LDS staging),       */
     int32_t kernel_groups;     /*   element groups of 4 waves per tile         */
 } das_plan_info;
 
@@ -192,7 +194,9 @@ const char *das_last_error(void);
 int das_version(void);
 
 /* The compiled beamforming kernel variants, as (frames per workgroup, LDS row
- * pitch, element groups) triples; das_plan_info reports which one a plan uses.
+ * pitch, element groups) triples, pitch 0 being the direct kernel (1 or 2
+ * frames per workgroup, no LDS staging); das_plan_info reports which one a
+ * plan uses.
  *   fc_pitch_groups  host int32 [3 * capacity] or NULL: receives the first
  *                    min(count, capacity) triples.
  *   capacity         >= 0 (0 with NULL asks for the count only).

@@ -464,7 +464,7 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
         d.fc = var.fc;
         d.pitch = var.pitch;
         d.groups = var.groups;
-        const int rows = var.pitch - 1;
+        const int rows = var.pitch > 0 ? var.pitch - 1 : INT32_MAX;  // the direct kernel takes whole windows
         std::vector<int32_t> win((size_t)2 * tl.n_tiles * T * E);
         if (!win.empty() &&
             ((e = hipMemcpyAsync(win.data(), d.windows, win.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=

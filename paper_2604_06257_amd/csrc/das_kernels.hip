@@ -484,6 +484,189 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     }
 }
 
+// ------------------------------------------------ direct kernel (1-2 frames)
+// With one or two frames per workgroup a staged window row serves only the few voxels that read it, once, and the
+// stage's fill and barrier cost more than they save.  This kernel reads each lane's two samples (rows i0 and
+// i0 + 1 of its frames) straight from the record through the buffer resource, whose range check returns zero
+// outside the record (the zero padding), and interpolates them: no LDS staging and no barrier between items.
+// Element groups split a tile's items and fold their partial sums in a fixed order at the end, as in
+// das_kernel.  The next item's coefficients and loads are issued before the current item's multiply-accumulate.
+template <int FC, int DT, int G, int NTX = 1>
+__global__ __launch_bounds__(kSlots* G) void das_direct_kernel(PlanDev p, const void* __restrict__ iq,
+                                                               float2* __restrict__ out, int vec, int64_t tx_stride) {
+    static_assert(FC == 1 || FC == 2, "direct kernel: 1 or 2 frames per workgroup");
+    constexpr int kEB = IQType<DT>::kBytes;
+    using Raw = typename RawT<FC * kEB>::type;  // FC consecutive frames of one sample row
+    const das_kparams& kp = p.kp;
+    const int nchunk = (kp.F + FC - 1) / FC;
+    const int unit = p.wg_unit[blockIdx.x];
+    const int tile = unit / nchunk;
+    const int f0 = (unit % nchunk) * FC;
+    const int grp = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kSlots));
+    const int gt = threadIdx.x % kSlots;
+    const int64_t slot = (int64_t)tile * kSlots + gt;
+    const int vox = p.slot_vox[slot];
+    const das_lane L = das_lane_setup(p.vx[slot], p.vy[slot], p.vz[slot], kp);
+    float acc_r[NTX * FC], acc_i[NTX * FC];
+#pragma unroll
+    for (int f = 0; f < NTX * FC; ++f) {
+        acc_r[f] = 0.0f;
+        acc_i[f] = 0.0f;
+    }
+    const int first = p.item_off[tile];
+    const int nitems = p.item_off[tile + 1] - first;
+    const int4* items = p.items + first;
+    const int64_t rec_bytes = (int64_t)kp.S * kp.F * kEB;
+    const int row_bytes = kp.F * kEB;
+    const int frame_off = f0 * kEB;
+    // whole-group loads when every row's group of FC frames is aligned (and complete); else sample by sample
+    const bool grouped = vec && (f0 + FC <= kp.F);
+    int last_e = -1, last_t = -1;
+    das_rx rx;
+    das_txc tc;
+    const das_txc tc0 = das_tx_const(p.tx[slot], kp);
+    auto coef = [&](const int4& it, auto one_tx) {
+        das_coef c;
+        if constexpr (decltype(one_tx)::value != 0) {
+            const double* e = p.elemd + 3 * it.y;
+            c = das_tx_setup(das_rx_setup_t<decltype(one_tx)::value == 1>(L, e[0], e[1], e[2], kp), tc0, kp);
+        } else {
+            if (__builtin_expect(it.y != last_e, 0)) {
+                const double* e = p.elemd + 3 * it.y;
+                rx = das_rx_setup(L, e[0], e[1], e[2], kp);
+                last_e = it.y;
+            }
+            if (it.x != last_t) {
+                tc = das_tx_const(p.tx[(int64_t)it.x * kp.n_slots + slot], kp);
+                last_t = it.x;
+            }
+            c = das_tx_setup(rx, tc, kp);
+        }
+        // lanes whose row is outside the item's window add exact zeros (rows in a window are in the record)
+        const unsigned d = (unsigned)c.i0 - (unsigned)it.z;
+        const bool use = d < (unsigned)it.w;
+        c.row = use ? c.i0 : -2;  // row -2 reads as zero
+        c.t = it.x;
+        c.cr = use ? c.cr : 0.0f;
+        c.ci = use ? c.ci : 0.0f;
+        return c;
+    };
+    // samples (rows i0 and i0 + 1, this chunk's frames) of an item for this lane
+    auto load = [&](const int4& it, const das_coef& c, Raw& q0, Raw& q1) {
+        const char* rec = reinterpret_cast<const char*>(iq) + ((int64_t)it.x * kp.E + it.y) * rec_bytes;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
+        // 32-bit offsets: a negative row wraps to an offset past the record, which reads as zero
+        const int off = c.row * row_bytes + frame_off;
+        if (grouped) {
+            if constexpr (sizeof(Raw) == 16) {
+                q0 = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+                q1 = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rs, off + row_bytes, 0, 0));
+            } else if constexpr (sizeof(Raw) == 8) {
+                q0 = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+                q1 = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rs, off + row_bytes, 0, 0));
+            } else {
+                q0 = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                q1 = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b32(rs, off + row_bytes, 0, 0));
+            }
+        } else {
+            uint32_t* w0 = reinterpret_cast<uint32_t*>(&q0);
+            uint32_t* w1 = reinterpret_cast<uint32_t*>(&q1);
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                if (kEB == 8) {
+                    const auto a = __builtin_amdgcn_raw_buffer_load_b64(rs, off + f * 8, 0, 0);
+                    const auto b = __builtin_amdgcn_raw_buffer_load_b64(rs, off + row_bytes + f * 8, 0, 0);
+                    w0[2 * f] = (uint32_t)a[0];
+                    w0[2 * f + 1] = (uint32_t)a[1];
+                    w1[2 * f] = (uint32_t)b[0];
+                    w1[2 * f + 1] = (uint32_t)b[1];
+                } else {
+                    w0[f] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + f * 4, 0, 0);
+                    w1[f] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, off + row_bytes + f * 4, 0, 0);
+                }
+            }
+        }
+    };
+    auto mac_into = [&](const das_coef& c, const Raw& q0, const Raw& q1, int a0) {
+#pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            const float2 a = decode<DT>(q0, f), b = decode<DT>(q1, f);
+            const float tr = fmaf(c.beta, b.x - a.x, a.x);
+            const float ti = fmaf(c.beta, b.y - a.y, a.y);
+            acc_r[a0 + f] = fmaf(c.cr, tr, acc_r[a0 + f]);
+            acc_r[a0 + f] = fmaf(-c.ci, ti, acc_r[a0 + f]);
+            acc_i[a0 + f] = fmaf(c.cr, ti, acc_i[a0 + f]);
+            acc_i[a0 + f] = fmaf(c.ci, tr, acc_i[a0 + f]);
+        }
+    };
+    auto mac = [&](const das_coef& c, const Raw& q0, const Raw& q1) {
+        if constexpr (NTX == 1) {
+            mac_into(c, q0, q1, 0);
+        } else {
+            const int t = __builtin_amdgcn_readfirstlane(c.t);
+#pragma unroll
+            for (int j = 0; j < NTX; ++j)
+                if (t == j) mac_into(c, q0, q1, j * FC);
+        }
+    };
+    auto run = [&](auto one_tx) {
+        if (grp >= nitems) return;
+        int4 it = items[grp];
+        das_coef c = coef(it, one_tx);
+        Raw q0, q1;
+        load(it, c, q0, q1);
+        for (int k = grp; k < nitems; k += G) {
+            das_coef cn = c;
+            Raw n0 = q0, n1 = q1;
+            if (k + G < nitems) {
+                const int4 itn = items[k + G];
+                cn = coef(itn, one_tx);
+                load(itn, cn, n0, n1);
+            }
+            mac(c, q0, q1);
+            c = cn;
+            q0 = n0;
+            q1 = n1;
+        }
+    };
+    if (kp.T > 1) run(std::integral_constant<int, 0>{});
+    else if (kp.planar) run(std::integral_constant<int, 1>{});
+    else run(std::integral_constant<int, 2>{});
+    if constexpr (G > 1) {
+        // fixed-order reduction of the groups' partial sums through LDS: ((g0 + g1) + g2) + ...
+        extern __shared__ float4 lds[];
+        float2* red = reinterpret_cast<float2*>(lds);  // [NTX * FC][kSlots]
+        for (int g = 1; g < G; ++g) {
+            __syncthreads();
+            if (grp == g) {
+#pragma unroll
+                for (int f = 0; f < NTX * FC; ++f) red[f * kSlots + gt] = make_float2(acc_r[f], acc_i[f]);
+            }
+            __syncthreads();
+            if (grp == 0) {
+#pragma unroll
+                for (int f = 0; f < NTX * FC; ++f) {
+                    const float2 v = red[f * kSlots + gt];
+                    acc_r[f] += v.x;
+                    acc_i[f] += v.y;
+                }
+            }
+        }
+    }
+    if (grp == 0 && vox >= 0) {
+#pragma unroll
+        for (int j = 0; j < NTX; ++j) {
+            if (NTX > 1 && j >= kp.T) break;
+            float2* o = out + j * tx_stride + (size_t)vox * kp.F;
+#pragma unroll
+            for (int f = 0; f < FC; ++f)
+                if (f0 + f < kp.F) o[f0 + f] = make_float2(acc_r[j * FC + f], acc_i[j * FC + f]);
+        }
+    }
+}
+
+// P = 0 denotes the direct kernel (no staging; LDS only for the group reduction).
 template <int FC, int P, int G, int NTX = 1>
 static size_t lds_bytes() {
     const size_t win = (size_t)G * 2 * FC * P * sizeof(float4);
@@ -506,35 +689,64 @@ static hipError_t launch_v(const PlanDev& p, const void* iq, int dtype, void* ou
     const size_t sh = lds_bytes<FC, P, G, NTX>();
     float2* o = reinterpret_cast<float2*>(out);
     const int64_t txs = (int64_t)p.n_vox * p.kp.F;
-    switch (dtype) {
-        case DAS_IQ_C64:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C64, G, NTX>), grid, block, sh, s, p, iq, o,
-                               vec_loads_ok<FC, DAS_IQ_C64>(p, iq), txs);
-            break;
-        case DAS_IQ_C16F:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16F, G, NTX>), grid, block, sh, s, p, iq, o,
-                               vec_loads_ok<FC, DAS_IQ_C16F>(p, iq), txs);
-            break;
-        default:
-            hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16BF, G, NTX>), grid, block, sh, s, p, iq, o,
-                               vec_loads_ok<FC, DAS_IQ_C16BF>(p, iq), txs);
-            break;
+    if constexpr (P == 0) {
+        switch (dtype) {
+            case DAS_IQ_C64:
+                hipLaunchKernelGGL((das_direct_kernel<FC, DAS_IQ_C64, G, NTX>), grid, block, sh, s, p, iq, o,
+                                   vec_loads_ok<FC, DAS_IQ_C64>(p, iq), txs);
+                break;
+            case DAS_IQ_C16F:
+                hipLaunchKernelGGL((das_direct_kernel<FC, DAS_IQ_C16F, G, NTX>), grid, block, sh, s, p, iq, o,
+                                   vec_loads_ok<FC, DAS_IQ_C16F>(p, iq), txs);
+                break;
+            default:
+                hipLaunchKernelGGL((das_direct_kernel<FC, DAS_IQ_C16BF, G, NTX>), grid, block, sh, s, p, iq, o,
+                                   vec_loads_ok<FC, DAS_IQ_C16BF>(p, iq), txs);
+                break;
+        }
+        return hipGetLastError();
+    } else {
+        switch (dtype) {
+            case DAS_IQ_C64:
+                hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C64, G, NTX>), grid, block, sh, s, p, iq, o,
+                                   vec_loads_ok<FC, DAS_IQ_C64>(p, iq), txs);
+                break;
+            case DAS_IQ_C16F:
+                hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16F, G, NTX>), grid, block, sh, s, p, iq, o,
+                                   vec_loads_ok<FC, DAS_IQ_C16F>(p, iq), txs);
+                break;
+            default:
+                hipLaunchKernelGGL((das_kernel<FC, P, DAS_IQ_C16BF, G, NTX>), grid, block, sh, s, p, iq, o,
+                                   vec_loads_ok<FC, DAS_IQ_C16BF>(p, iq), txs);
+                break;
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
 }
 
 template <int FC, int P, int G, int NTX = 1>
 static hipError_t set_lds_limit_ntx() {
     const int sh = (int)lds_bytes<FC, P, G, NTX>();
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C64, G, NTX>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
-        return e;
-    if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16F, G, NTX>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16BF, G, NTX>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, sh);
+    if constexpr (P == 0) {
+        if ((e = hipFuncSetAttribute((const void*)das_direct_kernel<FC, DAS_IQ_C64, G, NTX>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void*)das_direct_kernel<FC, DAS_IQ_C16F, G, NTX>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
+            return e;
+        return hipFuncSetAttribute((const void*)das_direct_kernel<FC, DAS_IQ_C16BF, G, NTX>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, sh);
+    } else {
+        if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C64, G, NTX>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
+            return e;
+        if ((e = hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16F, G, NTX>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, sh)) != hipSuccess)
+            return e;
+        return hipFuncSetAttribute((const void*)das_kernel<FC, P, DAS_IQ_C16BF, G, NTX>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, sh);
+    }
 }
 
 // Per-transmit output exists for the variants with at most 2 frames per workgroup.
@@ -560,16 +772,19 @@ static hipError_t launch_per_tx_v(const PlanDev& p, const void* iq, int dtype, v
 
 // Variants: FC = frames per workgroup (power of two), P = row pitch, G = groups.
 // FC * (P - 1) <= 2048 keeps the prefetch at <= 8 float4 per thread and the
-// frame stride inside the 16-bit LDS immediate offset.
+// frame stride inside the 16-bit LDS immediate offset.  P = 0: the direct
+// kernel (1 or 2 frames per workgroup, samples read without staging).
 #define DAS_VARIANTS(X)                                                                              \
     X(32, 41, 3) X(32, 49, 3) X(32, 33, 2) X(32, 65, 2) X(16, 33, 2) X(16, 65, 2) X(16, 129, 2) X(8, 33, 1) X(8, 65, 1)       \
     X(8, 129, 1) X(8, 257, 1) X(4, 33, 1) X(4, 65, 1) X(4, 129, 1) X(4, 257, 1) X(4, 513, 1) X(2, 129, 1)      \
     X(2, 257, 1) X(2, 513, 1) X(2, 1025, 1) X(1, 65, 1) X(1, 129, 1) X(1, 257, 1) X(1, 513, 1) X(1, 1025, 1) X(1, 2049, 1) \
     X(1, 65, 4) X(1, 129, 4) X(1, 257, 4) X(2, 129, 4) X(2, 257, 4) X(4, 65, 4) X(4, 129, 4) X(8, 65, 2) X(8, 65, 4) X(8, 33, 2) X(8, 129, 2) X(16, 65, 4) X(4, 65, 2) \
-    X(1, 65, 2) X(1, 129, 2) X(1, 257, 2) X(2, 129, 2) X(2, 257, 2) X(4, 129, 2) X(8, 129, 4)
+    X(1, 65, 2) X(1, 129, 2) X(1, 257, 2) X(2, 129, 2) X(2, 257, 2) X(4, 129, 2) X(8, 129, 4)                  \
+    X(1, 0, 1) X(1, 0, 2) X(1, 0, 4) X(2, 0, 1) X(2, 0, 2) X(2, 0, 4)
 
 // Variant choice (measured on MI355X with the c1 / c2 / c3 workloads and sweeps of grid size (64-1024 tiles),
 // frame count (1-24) and element count (64-256) around the c2 geometry):
+//  - one or two frames per workgroup take the direct kernel when tiles carry fewer than 1200 items;
 //  - frames are cut into chunks of FC; more chunks mean more workgroups, which
 //    the heaviest-first dispatch order balances, at the cost of forming the
 //    coefficients once per chunk;
@@ -591,11 +806,11 @@ static bool variant_exists(int fc, int pitch, int g) {
     return false;
 }
 
-// smallest pitch >= min_pitch with a (fc, pitch, g) variant, or 0
+// smallest pitch >= min_pitch with a (fc, pitch, g) variant, or -1 (pitch 0 is the direct kernel)
 static int pitch_at_least(int fc, int min_pitch, int g) {
-    int best = 0;
+    int best = -1;
 #define DAS_PIT(FC_, P_, G_) \
-    if (FC_ == fc && G_ == g && P_ >= min_pitch && (best == 0 || P_ < best)) best = P_;
+    if (FC_ == fc && G_ == g && P_ >= min_pitch && (best < 0 || P_ < best)) best = P_;
     DAS_VARIANTS(DAS_PIT)
 #undef DAS_PIT
     return best;
@@ -621,8 +836,13 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles, double items
     const int base_g = fc >= 16 ? 2 : 1;
     const int min_pitch = fc >= 8 ? 65 : 0;
     Variant best{0, 0, 0};
+    // the direct kernel for 1-2 frames unless tiles carry many items (3D apertures of many elements and
+    // transmits): there every item's 16 bytes per lane of gathers outweigh the staged window's few hundred
+    // (c2 grid, 1 frame: 0.0233 -> 0.0186 ms; c5 geometry, 11 angles: 5.47 -> 7.23 ms)
+    const bool direct = fc <= 2 && items_per_tile < 1200.0 && variant_exists(fc, 0, base_g);
+    if (direct) best = {fc, 0, base_g};
 #define DAS_PICK(FC_, P_, G_)                                                                       \
-    if (FC_ == fc && G_ == base_g && P_ >= min_pitch) {                                             \
+    if (!direct && FC_ == fc && G_ == base_g && P_ >= min_pitch && P_ > 0) {                        \
         if (best.fc == 0 || (best.pitch - 1 < max_window && P_ > best.pitch)) best = {FC_, P_, G_}; \
     }
     DAS_VARIANTS(DAS_PICK)
@@ -631,7 +851,7 @@ Variant choose_variant(int frames, int max_window, int64_t n_tiles, double items
     const int64_t target = items_per_tile >= 1024.0 ? 8192 : (best.fc <= 4 ? 6144 : 2560);
     for (int g = base_g; g <= 4; g *= 2) {
         const int p = pitch_at_least(best.fc, best.pitch, g);
-        if (p != 0 && (n_tiles * chunks(best.fc) * 4 * g >= target || g == 4)) return Variant{best.fc, p, g};
+        if (p >= 0 && (n_tiles * chunks(best.fc) * 4 * g >= target || g == 4)) return Variant{best.fc, p, g};
     }
     return best;
 }

@@ -44,7 +44,10 @@ def test_kernel_variants_list():
     assert len(vs) == n and len(set(vs)) == n
     for fc, pitch, groups in vs:
         assert fc in (1, 2, 4, 8, 16, 32)
-        assert pitch % 2 == 1 and fc * (pitch - 1) <= 2048  # odd pitch; prefetch and LDS offset bounds
+        if pitch == 0:  # the direct kernel (no staging): 1 or 2 frames per workgroup
+            assert fc <= 2
+        else:
+            assert pitch % 2 == 1 and fc * (pitch - 1) <= 2048  # odd pitch; prefetch and LDS offset bounds
         assert groups in (1, 2, 3, 4)
     short = (ctypes.c_int32 * 3)()
     assert lib.das_kernel_variants(short, 1) == n
@@ -56,7 +59,9 @@ def test_kernel_variants_list():
 @pytest.mark.parametrize("figures,expected", [
     ((32, 35, 256, 70.0), (16, 65, 2)),      # c2: 256 tiles, 16-frame chunks, two element groups
     ((8, 43, 3456, 1838.0), (8, 65, 1)),     # c3: one unpaired 8-frame chunk per tile, one group fills the chip
-    ((1, 100, 64, 60.0), (1, 129, 4)),       # c1: 64 tiles, groups added up to 4, pitch holds the window
+    ((1, 100, 64, 60.0), (1, 0, 4)),         # c1: 64 tiles, the direct kernel, groups added up to 4
+    ((2, 35, 256, 70.0), (2, 0, 4)),         # c2 grid with 2 frames: the direct kernel
+    ((1, 43, 3456, 1100.0), (1, 0, 1)),      # c5 geometry, 3 transmits: the direct kernel, one group fills the chip
     ((6, 43, 2000, 500.0), (8, 65, 1)),      # 5-8 frames always take 8-frame chunks
     ((16, 35, 64, 70.0), (4, 65, 4)),        # few tiles: the chunk halves until 256 workgroups (64 x 4)
     ((64, 35, 1024, 70.0), (32, 41, 3)),     # F >= 32 on many tiles: 32-frame chunks, short windows
