@@ -72,12 +72,26 @@ def measured_traffic(workload):
     return int(f["read_bytes"]) + int(f["write_bytes"])
 
 
-def _cores():
+def _host_cpus():
+    """(os.cpu_count(), the CPUs in this process's affinity mask, as a compact range list)."""
     try:
-        n = len(os.sched_getaffinity(0))
+        aff = sorted(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+        aff = list(range(os.cpu_count() or 1))
+    runs, start = [], None
+    for i, c in enumerate(aff):
+        if start is None:
+            start = c
+        if i + 1 == len(aff) or aff[i + 1] != c + 1:
+            runs.append("%d" % start if start == c else "%d-%d" % (start, c))
+            start = None
+    return os.cpu_count(), aff, ",".join(runs)
+
+
+def _cores():
+    """Worker processes for the oracle: the CPUs this process may run on, at most 16 (the machine's CPU share
+    of one GPU)."""
+    return max(1, min(16, len(_host_cpus()[1])))
 
 
 _SHARED = {}
@@ -123,8 +137,23 @@ def cpu_baseline(cfg, max_voxels, min_seconds=10.0):
         y[a:a + part.shape[0]] = part
     T, E = cfg["iq"].shape[:2]
     pts = V * E * T * p["n_frames"]
+    # one core: the first voxels of the same sample in this process, repeated for about 3 s
+    n1 = max(1, V // 64)
+    reps1, t1 = 0, time.perf_counter()
+    while True:
+        _oracle_chunk((0, n1))
+        reps1 += 1
+        if time.perf_counter() - t1 >= 3.0:
+            break
+    dt1 = time.perf_counter() - t1
+    pts1 = n1 * E * T * p["n_frames"]
+    n_cpu, aff, aff_txt = _host_cpus()
     return y, {"value": reps * pts / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
                "seconds": round(dt, 3), "repeats": reps,
+               "host_cpu_count": n_cpu, "affinity_cpus": len(aff), "affinity_mask": aff_txt,
+               "single_core": {"value": reps1 * pts1 / dt1, "unit": "points/s", "seconds": round(dt1, 3),
+                               "sample": "%d voxels x all elements, transmits, frames = %d points, %d times"
+                                         % (n1, pts1, reps1)},
                "sample": "%d voxels (all %d elements, %d transmit(s), %d frames) = %d points, computed %d times, "
                          "voxel chunks over %d processes" % (V, E, T, p["n_frames"], pts, reps, cores)}
 
@@ -223,6 +252,42 @@ def scaling_sweep(axis, steps, warmup):
         del iq, out
 
 
+def c3_report(steps, warmup, torch, das, oracle):
+    """c3 (the largest single-GPU workload: 96^3 voxels, 32 x 32 elements, 5 plane waves, 8 frames) timed in
+    the same run: channel data from the GPU echo simulator (the input generator's model), the plan's variant, ms
+    per launch, points/s (Eq. 1), the roofline fraction of its kernel and the error against the FP64 oracle on
+    a sample of voxels."""
+    from synth import echo_iq_gpu
+    cfg = make_config("c3", with_iq=False)
+    p = cfg["params"]
+    T, E, S, F = cfg["angles"].shape[0], cfg["elem"].shape[0], p["n_samples"], p["n_frames"]
+    V = cfg["vox"].shape[0]
+    iq = echo_iq_gpu(cfg["elem"], cfg["angles"], cfg["scat"], cfg["amp"], n_samples=S, n_frames=F, c=p["c"],
+                     fs=p["fs"], fc=p["fc"], fd=p["fd"], t0=p["t0"])
+    vox = torch.from_numpy(cfg["vox"]).cuda()
+    tx = das.tx_plane_wave(vox, cfg["angles"], p["c"])
+    params = das.Params(T, E, S, F, V, p["c"], p["fs"], p["fd"], p["t0"], p["f_number"], p["tukey_alpha"])
+    with das.Plan(params, torch.from_numpy(cfg["elem"]).cuda(), vox, tx) as plan:
+        info = plan.info()
+        out = torch.empty((V, F), dtype=torch.complex64, device="cuda")
+        ms, _ = time_steps(plan, iq, out, steps, warmup, torch)
+        y = out.cpu().numpy()
+    idx = np.arange(0, V, V // 48)[:48]  # 48 voxels spread over the grid
+    ref = oracle.das(iq.cpu().numpy(), cfg["elem"], cfg["vox"][idx], tx.cpu().numpy()[:, idx], c=p["c"], fs=p["fs"],
+                     fd=p["fd"], t0=p["t0"], f_number=p["f_number"], tukey_alpha=p["tukey_alpha"])
+    pts = V * E * T * F
+    tflops = info["active_triples"] * F * FLOP_PER_POINT / (ms * 1e-3) / 1e12
+    return {"workload": "c3: " + WORKLOADS["c3"], "ms_per_step": ms, "value": pts / (ms * 1e-3),
+            "unit": "points/s", "points_per_step": pts,
+            "active_points_per_s": info["active_triples"] * F / (ms * 1e-3),
+            "kernel": "das_kernel<fc=%d, pitch=%d, groups=%d>" % info["kernel"],
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / PEAK_FP32_TFLOPS, "traffic": measured_traffic("c3")},
+            "nrmse_db_vs_fp64": oracle.nrmse_db(y[idx], ref), "peak_err_db_vs_fp64": oracle.peak_err_db(y[idx], ref),
+            "parity_sample": "%d voxels (every %d-th), all elements, transmits and frames" % (len(idx), V // 48),
+            "iq": "GPU echo simulator: 20000 speckle scatterers per frame + 50 points"}
+
+
 def hbm_report(T, E, S, F, V, info, ms, traffic):
     """The HBM side of the roofline for one launch: compulsory bytes (IQ read once, output written once, the
     transmit table and the voxel and element coordinates), their rate against the 8 TB/s peak, the measured HBM
@@ -246,6 +311,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP16 / BF16 IQ timings")
+    ap.add_argument("--no-c3", action="store_true", help="skip the c3 sub-object")
     ap.add_argument("--cpu-voxels", type=int, default=None, help="voxels in the oracle sample (default: all)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a torch copy of this many GiB (for HBM counter calibration)")
@@ -354,6 +420,9 @@ def main():
             del iq16
         var["iq_range"] = iq16_range(iq_np)
         result["iq16_variants"] = var
+    if not args.no_c3 and args.workload != "c3":
+        result["c3"] = c3_report(max(5, args.steps // 10), max(2, args.warmup // 4), torch, das, oracle)
+        torch.cuda.empty_cache()
     if args.post:
         from paper_2604_06257_amd import post
         plan.execute(iq, out)

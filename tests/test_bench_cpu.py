@@ -62,3 +62,16 @@ def test_hbm_report_compulsory_bytes():
     assert abs(r["frac"] - r["compulsory_GBps"] / 8000.0) < 1e-12
     assert r["measured_GBps"] is None and r["gather_GBps"] == 1000 * 32 * 16 / 1e-4 / 1e9
     assert bench.hbm_report(1, 128, 2048, 32, 65536, info, 0.1, 2e8)["measured_GBps"] == 2e8 / 1e-4 / 1e9
+
+
+def test_host_cpu_report():
+    """cpu_baseline states the host's CPU count and the affinity mask the oracle pool runs on (as ranges)."""
+    import bench
+    n, aff, txt = bench._host_cpus()
+    assert n >= 1 and len(aff) >= 1 and set(aff) <= set(range(max(n, max(aff) + 1)))
+    expanded = []
+    for part in txt.split(","):
+        a, _, b = part.partition("-")
+        expanded += list(range(int(a), int(b or a) + 1))
+    assert expanded == aff
+    assert 1 <= bench._cores() <= min(16, len(aff))
