@@ -39,8 +39,11 @@ int64_t das_bmode_work(int64_t V, int F);
 /* Power Doppler with an SVD clutter filter:
  *   pd[v] = sum_f |(C - U_k S_k V_k^H)[v][f]|^2 = |c_v|^2 - sum_{j<k} |c_v . v_j|^2
  * where C = y [V][F], v_j are its right singular vectors in order of decreasing
- * singular value (eigenvectors of C^H C from a float64 Jacobi solver) and
- * k = n_clutter (0 <= k <= F; k = 0 gives the frame energy).  float32 [V]
+ * singular value and k = n_clutter (0 <= k <= F; k = 0 gives the frame energy,
+ * k = F zero).  For 0 < k < F the k eigenvectors of C^H C with the largest
+ * eigenvalues come from a float64 solver (Householder tridiagonalisation, Sturm
+ * multisection, twisted-factorisation eigenvectors; a spectrum with repeated
+ * eigenvalues among the k largest takes a Jacobi solver instead).  float32 [V]
  * output, float64 arithmetic.  work holds das_power_doppler_work(V, F)
  * doubles, 16-byte aligned (its contents on return are internal).  DAS_ESHAPE unless V >= 1
  * and 1 <= F <= 32; DAS_EINVAL unless 0 <= n_clutter <= F. */

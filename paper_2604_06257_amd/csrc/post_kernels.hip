@@ -7,10 +7,12 @@
 //
 // Power Doppler: the right singular vectors of the Casorati matrix C = y are the
 // eigenvectors of the Gram matrix G = C^H C (F x F, Hermitian).  G is summed in
-// float64 over voxel chunks (partials added in chunk order: deterministic), then
-// diagonalised by one workgroup with the parallel cyclic Jacobi method (round-
-// robin ordering: F/2 disjoint rotations at a time, each a complex phase
-// followed by a real plane rotation).  The energy a voxel keeps after removing
+// float64 over voxel chunks (partials added in chunk order: deterministic).  Only
+// the k eigenvectors of the largest eigenvalues are needed: one workgroup reduces
+// G to a real tridiagonal matrix (Householder), finds those eigenvalues by Sturm
+// multisection and their eigenvectors by twisted factorisations, and transforms
+// them back; a spectrum that fails its residual or orthogonality checks takes the
+// parallel cyclic Jacobi method instead.  The energy a voxel keeps after removing
 // the k largest components is |c|^2 - sum_{j<k} |c . v_j|^2, evaluated in float64.
 #include <hip/hip_runtime.h>
 
@@ -136,13 +138,14 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 // Round-robin position: element 0 stays, the others rotate by one place per step.
 __device__ __forceinline__ int rr(int i, int s, int n) { return i == 0 ? 0 : ((i - 1 + s) % (n - 1)) + 1; }
 
-// G = sum_b part[b]; eigenvectors by parallel cyclic Jacobi; vec[f][j] = eigenvector j (descending eigenvalues).
-// NT threads (256 measured faster than one 64-lane wave: the update pass dominates a step).  The pair schedule
-// and every thread's update indices are formed once, outside the sweeps.
+// Every eigenvector of G (F x F, row-major) by parallel cyclic Jacobi; vec[f][j] = eigenvector j (descending
+// eigenvalues), eval[j] its eigenvalue.  Called by all NT threads of the workgroup (256 measured faster than one
+// 64-lane wave: the update pass dominates a step).  The pair schedule and every thread's update indices are formed
+// once, outside the sweeps.  Robust for any spectrum (repeated eigenvalues included), but a chain of ~F/2 * 10
+// dependent rotation steps: the fallback of the top-k solver below.
 template <int NT>
-__global__ __launch_bounds__(NT) void jacobi_kernel(const double2* __restrict__ part, int nb, int F,
-                                                    double2* __restrict__ vec, double* __restrict__ eval,
-                                                    int max_sweeps) {
+__device__ void jacobi_solve(const double2* __restrict__ g, int F, double2* __restrict__ vec,
+                             double* __restrict__ eval, int max_sweeps) {
     constexpr int kQItems = (kMaxF / 2 * kMaxF + NT - 1) / NT;  // Q-update items per thread
     __shared__ double2 A[kMaxF][kMaxF + 1];
     __shared__ double2 Q[kMaxF][kMaxF + 1];
@@ -155,10 +158,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double2* __restrict__ 
     const int half = n / 2;
     for (int pr = threadIdx.x; pr < n * n; pr += NT) {
         const int i = pr / n, j = pr % n;
-        double2 g = make_double2(0.0, 0.0);
-        if (i < F && j < F)
-            for (int b = 0; b < nb; ++b) g = cadd(g, part[(int64_t)b * F * F + i * F + j]);
-        A[i][j] = g;
+        A[i][j] = (i < F && j < F) ? g[i * F + j] : make_double2(0.0, 0.0);
         Q[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     for (int w = threadIdx.x; w < (n - 1) * half; w += NT) {
@@ -273,14 +273,411 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const double2* __restrict__ 
     for (int j = threadIdx.x; j < F; j += NT) eval[j] = A[order[j]][order[j]].x;
 }
 
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b) { return c ? a : b; }
+
+// Cross-lane moves of a double: DPP within rows of 16 lanes (a VALU operand modifier, no LDS round trip), the
+// swizzle for the two rows of a 32-lane half.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), kCtrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swap16_d(double x) {  // lane i <-> lane i ^ 16
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowHalfMirror = 0x141, kRowMirror = 0x140;
+// Sums over aligned groups of 8 and of 32 lanes; every lane of the group gets the same value (each step adds a
+// lane's value and its partner's, which both lanes form alike).
+__device__ __forceinline__ double sum8(double x) {
+    x += dpp_d<kQuadXor1>(x);
+    x += dpp_d<kQuadXor2>(x);
+    return x + dpp_d<kRowHalfMirror>(x);
+}
+__device__ __forceinline__ double sum32(double x) {
+    x = sum8(x);
+    x += dpp_d<kRowMirror>(x);
+    return x + swap16_d(x);
+}
+
+// Number of eigenvalues below sig of the symmetric tridiagonal T (diagonal d, squared off-diagonal e2[i] =
+// e_{i-1}^2, e_{-1} = 0; |T| <= 1), for kP points at once: the sign changes of the Sturm sequence of leading
+// principal minors p_i = (d_{i-1} - sig) p_{i-1} - e_{i-2}^2 p_{i-2}, p_0 = 1 (one eigenvalue below sig per
+// negative ratio p_i / p_{i-1}).  No division: the chain is one FMA per step; every four steps both carried
+// minors are rescaled by the same power of two (exact, signs kept), so no minor overflows or underflows.  The
+// kP chains are independent and interleave.
+template <int kP>
+__device__ __forceinline__ void sturm_counts(const double (&d)[kMaxF], const double (&e2)[kMaxF],
+                                             const double (&sig)[kP], int (&c)[kP]) {
+    double p[kP], pp[kP];
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+        p[q] = 1.0;
+        pp[q] = 0.0;
+        c[q] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxF; ++i) {
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+            const double pn = fma(d[i] - sig[q], p[q], -e2[i] * pp[q]);
+            c[q] += (pn * p[q] < 0.0) ? 1 : 0;
+            pp[q] = p[q];
+            p[q] = pn;
+            if ((i & 3) == 3) {
+                const int ex = __builtin_amdgcn_frexp_exp(p[q]);
+                p[q] = __builtin_ldexp(p[q], -ex);
+                pp[q] = __builtin_ldexp(pp[q], -ex);
+            }
+        }
+    }
+}
+
+// 1 / x from the hardware reciprocal and two Newton steps (within an ulp or so; x finite and nonzero)
+__device__ __forceinline__ double rcp_d(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// The k eigenvectors of the largest eigenvalues of the Hermitian G (F x F, row-major), 0 < k < F <= 32, for the
+// clutter filter: vec[f][j] = eigenvector j (descending eigenvalues), eval[j] its eigenvalue, j < k.  One
+// workgroup of 256 threads; thread t holds entries (t / 8, t % 8 + 8u), u < 4, of G and of Q in registers, so a
+// row's eight threads reduce over the row with DPP moves.
+//   1. Householder reduction of G to a real symmetric tridiagonal T = Q^H G Q (one reflector per column, whose
+//      coefficient makes the sub-diagonal real: H = I - tau v v^H with H^H x = beta e_1, beta real), the trailing
+//      block updated as B - w v^H - v w^H with w = tau B v - (|tau|^2 / 2)(v^H B v) v, and Q as Q - tau (Q v) v^H;
+//   2. the k largest eigenvalues of T by multisection on Sturm counts (a group of up to 64 lanes per eigenvalue,
+//      two counts per lane and round; ballots give the new bracket) until the bracket stops shrinking;
+//   3. each eigenvector of T from the twisted factorisation of T - lambda I (forward and backward pivots, the
+//      twist at the smallest |gamma_r|, then the two product recurrences away from r), normalised;
+//   4. checks: every residual |(T - lambda) z|_i <= 1e-11 |T| and every |z_a . z_b| <= 1e-10; then one classical
+//      Gram-Schmidt pass against the vectors of larger eigenvalues;
+//   5. v = Q z.
+// A spectrum that fails a check (eigenvalues repeated among the k largest, non-finite input) takes the Jacobi
+// solver instead, for the same output.  Every reduction is in a fixed order: the result is deterministic.
+__global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict__ g, int F, int k,
+                                                      double2* __restrict__ vec, double* __restrict__ eval) {
+    constexpr int NT = 256;
+    __shared__ double2 COL[kMaxF];  // column j of the partly reduced matrix (conjugate of row j): reflector j's input
+    // The current reflector, offset by one with a zero in front and zeros past its length, so that rows and
+    // columns outside the trailing block update by exact zeros: HVp[1 + i] = v_i, TVC[1 + i] = tau conj(v_i),
+    // PVp[1 + i] = p_i = (B v)_i, CPp[1 + i] = conj(tau p_i); UV[r] = (Q v)_r; SW = partial sums of v^H p.
+    __shared__ double2 HVp[kMaxF + 1], TVC[kMaxF + 1], PVp[kMaxF + 1], CPp[kMaxF + 1];
+    __shared__ double2 UV[kMaxF];
+    __shared__ double SW[NT / 32];
+    __shared__ double2 TAU[kMaxF];
+    __shared__ double Dg[kMaxF], Ef[kMaxF], LAM[kMaxF];
+    __shared__ double PIV[2][kMaxF][kMaxF + 1];  // [0] forward pivots D+_i, [1] backward pivots D-_i per eigenvalue
+    __shared__ double RAT[2][kMaxF][kMaxF + 1];  // [0] e_i / D+_i, [1] e_{i-1} / D-_i
+    __shared__ double Z[kMaxF][kMaxF + 1];       // tridiagonal eigenvectors, Z[j][i]
+    __shared__ double M[kMaxF][kMaxF + 1];       // Z Z^T
+    __shared__ int TW[kMaxF];
+    __shared__ int bad;
+    const int n = F, t = threadIdx.x;
+    const int r = t >> 3, l = t & 7;  // this thread's row and first column
+    double2 a[4], qm[4];              // G (being reduced) and Q at (r, l + 8u)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = l + 8 * u;
+        const bool in = r < n && c < n;
+        a[u] = in ? g[r * n + c] : make_double2(0.0, 0.0);
+        qm[u] = make_double2(in && r == c ? 1.0 : 0.0, 0.0);
+    }
+    // the owners of row 0 publish column 0 (the conjugate of row 0)
+    if (r == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (l + 8 * u < n) COL[l + 8 * u] = cconj(a[u]);
+    }
+    if (t == 0) {
+        bad = 0;
+        HVp[0] = TVC[0] = PVp[0] = CPp[0] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    // 1. tridiagonalisation
+    for (int j = 0; j + 1 < n; ++j) {
+        const int m = n - 1 - j;  // length of the column below the diagonal
+        if (t < 32) {
+            const double2 x = t < m ? COL[j + 1 + t] : make_double2(0.0, 0.0);
+            const double sq = sum32((t >= 1 && t < m) ? fma(x.x, x.x, x.y * x.y) : 0.0);
+            const double ar = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x.x)),
+                                               __builtin_amdgcn_readfirstlane(__double2loint(x.x)));
+            const double ai = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x.y)),
+                                               __builtin_amdgcn_readfirstlane(__double2loint(x.y)));
+            double2 tau = make_double2(0.0, 0.0), sc = make_double2(0.0, 0.0);
+            double beta = ar;
+            if (sq != 0.0 || ai != 0.0) {
+                beta = -copysign(sqrt(fma(ar, ar, fma(ai, ai, sq))), ar);
+                const double ib = rcp_d(beta);
+                tau = make_double2((beta - ar) * ib, -ai * ib);
+                const double dr = ar - beta, iden = rcp_d(fma(dr, dr, ai * ai));  // 1 / (alpha - beta)
+                sc = make_double2(dr * iden, -ai * iden);
+            }
+            const double2 v = t < m ? (t == 0 ? make_double2(1.0, 0.0) : cmul(x, sc)) : make_double2(0.0, 0.0);
+            HVp[1 + t] = v;
+            TVC[1 + t] = cmul(tau, cconj(v));
+            if (t == 0) {
+                TAU[j] = tau;
+                Ef[j] = beta;
+                Dg[j] = COL[j].x;
+            }
+        }
+        __syncthreads();
+        const double2 tau = TAU[j];
+        const bool live = tau.x != 0.0 || tau.y != 0.0;  // uniform; H = I otherwise
+        const int cn = j + 1;                            // the next column
+        if (live) {
+            // p = B v and u = Q v, row by row: this thread's four columns, then the row's eight threads
+            double2 pa = make_double2(0.0, 0.0), pq = pa;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = l + 8 * u;
+                const double2 hv = HVp[c > j ? c - j : 0];
+                pa = cadd(pa, cmul(a[u], hv));
+                pq = cadd(pq, cmul(qm[u], hv));
+            }
+            pa.x = sum8(pa.x);
+            pa.y = sum8(pa.y);
+            pq.x = sum8(pq.x);
+            pq.y = sum8(pq.y);
+            const int ri = r > j ? r - j : 0;  // row r's slot in the padded arrays (0: outside the block)
+            const double2 vr = HVp[ri];
+            // v^H p (real: B is Hermitian): each half-wave's four rows, summed in a fixed order below
+            const double hs = sum32(l == 0 ? fma(vr.x, pa.x, vr.y * pa.y) : 0.0);
+            if ((t & 31) == 0) SW[t >> 5] = hs;
+            if (l == 0) {
+                UV[r] = pq;
+                if (r > j) {
+                    PVp[ri] = pa;
+                    CPp[ri] = cconj(cmul(tau, pa));
+                }
+            }
+            __syncthreads();
+            const double sv = ((SW[0] + SW[1]) + (SW[2] + SW[3])) + ((SW[4] + SW[5]) + (SW[6] + SW[7]));
+            const double h2 = fma(tau.x, tau.x, tau.y * tau.y) * sv;  // 2 h = |tau|^2 v^H p
+            // B[r][c] -= w_r conj(v_c) + v_r conj(w_c) with w = tau p - h v, i.e. X_r conj(v_c) + v_r conj(tau p_c)
+            // with X_r = tau p_r - 2 h v_r; Q[r][c] -= u_r tau conj(v_c)
+            const double2 xr = csub(cmul(tau, PVp[ri]), cscale(vr, h2));
+            const double2 ur = UV[r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = l + 8 * u, ci = c > j ? c - j : 0;
+                const double2 cv = cconj(HVp[ci]);
+                a[u] = csub(a[u], cadd(cmul(xr, cv), cmul(vr, CPp[ci])));
+                qm[u] = csub(qm[u], cmul(ur, TVC[ci]));
+            }
+        }
+        // the owners of row cn publish column cn (its conjugate; the matrix is Hermitian), final from here on
+        if (r == cn) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (l + 8 * u < n) COL[l + 8 * u] = cconj(a[u]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) Dg[n - 1] = COL[n - 1].x;
+    __syncthreads();
+    // T in registers (scaled by 2^-sx, exact, so that |T| <= 1), |T| and the Gershgorin interval; alike in
+    // every thread.  Rows past n are decoupled copies of the largest diagonal bound: no count changes there.
+    double dv[kMaxF], e2v[kMaxF];
+    double tn = 0.0, lo = 1.0 / 0.0, hi = -1.0 / 0.0;
+#pragma unroll
+    for (int i = 0; i < kMaxF; ++i) {
+        const double di = i < n ? Dg[i] : 0.0;
+        const double el = (i > 0 && i < n) ? fabs(Ef[i - 1]) : 0.0, er = i + 1 < n ? fabs(Ef[i]) : 0.0;
+        dv[i] = di;
+        e2v[i] = el * el;
+        if (i < n) {
+            lo = fmin(lo, di - el - er);
+            hi = fmax(hi, di + el + er);
+            tn = fmax(tn, fabs(di) + el + er);
+        }
+    }
+    const int sx = tn > 0.0 ? __builtin_amdgcn_frexp_exp(tn) : 0;
+    const double sc1 = __builtin_ldexp(1.0, -sx);  // |T| sc1 in [0.5, 1)
+    lo = fma(-1e-14, tn, lo) * sc1 - 1e-300;
+    hi = fma(1e-14, tn, hi) * sc1 + 1e-300;
+#pragma unroll
+    for (int i = 0; i < kMaxF; ++i) {
+        dv[i] = i < n ? dv[i] * sc1 : 2.0;  // beyond every bracket point
+        e2v[i] = i < n ? e2v[i] * sc1 * sc1 : 0.0;
+    }
+
+    // 2. the k largest eigenvalues: groups of tpe lanes (a power of two <= 64, inside one wave); lane q of a group
+    // counts at the points (p tpe + q + 1) / (kP tpe + 1) of the bracket, p < kP; counts grow with the point, so
+    // the points below the eigenvalue are the first `below` of the group's kP tpe points and the new bracket lies
+    // between points below - 1 and below
+    {
+        constexpr int kP = 2;
+        int tpe = 64;
+        while (tpe * k > NT && tpe > 1) tpe >>= 1;
+        const int grp = t / tpe, q = t % tpe, gbase = (t & 63) - q;
+        const uint64_t gmask = tpe == 64 ? ~0ull : ((1ull << tpe) - 1ull);
+        const bool active = grp < k;
+        const int idx = active ? n - 1 - grp : 0;  // eigenvalue index in ascending order
+        const int npts = kP * tpe;
+        const double step = 1.0 / (double)(npts + 1);
+        for (int it = 0; it < 200; ++it) {
+            const double w = hi - lo;
+            double sig[kP];
+            int cnt[kP];
+#pragma unroll
+            for (int p = 0; p < kP; ++p) sig[p] = fma(w, (double)(p * tpe + q + 1) * step, lo);
+            sturm_counts<kP>(dv, e2v, sig, cnt);
+            int below = 0;
+#pragma unroll
+            for (int p = 0; p < kP; ++p) below += __popcll((__ballot(cnt[p] <= idx) >> gbase) & gmask);
+            const double nlo = below > 0 ? fma(w, (double)below * step, lo) : lo;
+            const double nhi = below < npts ? fma(w, (double)(below + 1) * step, lo) : hi;
+            const bool done = !active || (nlo == lo && nhi == hi);
+            lo = nlo;
+            hi = nhi;
+            if (__all(done)) break;
+        }
+        if (active && q == 0) LAM[grp] = __builtin_ldexp(0.5 * (lo + hi), sx);
+    }
+    const double pivmin = 1e-290 * fmax(1.0, tn * tn);
+    __syncthreads();
+
+    // 3. twisted factorisations: lane 2j runs the forward pivots of eigenvalue j, lane 2j + 1 the backward ones,
+    // as one instruction stream (index i = s forward, n - 1 - s backward)
+    if (t < 2 * k) {
+        const int j = t >> 1, dir = t & 1;
+        const double lam = LAM[j];
+        double dpv = Dg[dir ? n - 1 : 0] - lam;
+#pragma unroll
+        for (int s = 0; s + 1 < kMaxF; ++s) {
+            const bool live = s + 1 < n;
+            const int sc = live ? s : 0, i = dir ? n - 1 - sc : sc, inext = dir ? i - 1 : i + 1;
+            const double e = Ef[dir ? i - 1 : i], dn = Dg[inext];  // e: the off-diagonal between i and inext
+            const double rl = e * rcp_d(dpv != 0.0 ? dpv : pivmin);
+            if (live) {
+                PIV[dir][j][i] = dpv;
+                RAT[dir][j][i] = rl;
+            }
+            dpv = live ? fma(-rl, e, dn - lam) : dpv;
+        }
+        PIV[dir][j][dir ? 0 : n - 1] = dpv;
+    }
+    __syncthreads();
+    // twist index: the smallest |gamma_i| = |D+_i + D-_i - (d_i - lambda)|, ties to the lower index; 32 lanes each
+    for (int j = t >> 5; j < k; j += NT / 32) {
+        const int i = t & 31;
+        double av = 1.0 / 0.0;
+        if (i < n) {
+            const double gm = fabs(PIV[0][j][i] + PIV[1][j][i] - (Dg[i] - LAM[j]));
+            av = gm <= 1.7e308 ? gm : 1.0 / 0.0;
+        }
+        int ia = i;
+        for (int o = 16; o > 0; o >>= 1) {
+            const double b = __shfl_xor(av, o);
+            const int ib = __shfl_xor(ia, o);
+            if (b < av || (b == av && ib < ia)) {
+                av = b;
+                ia = ib;
+            }
+        }
+        if (i == 0) TW[j] = ia;
+    }
+    __syncthreads();
+    if (t < 2 * k) {  // z_r = 1, then lane 2j goes up (z_i = -(e_i / D+_i) z_{i+1}), lane 2j + 1 down
+        const int j = t >> 1, dir = t & 1, rt = TW[j];
+        double z = 1.0;
+        if (dir == 0) Z[j][rt] = 1.0;
+#pragma unroll
+        for (int s = 1; s < kMaxF; ++s) {
+            const int i = dir ? rt + s : rt - s;
+            const bool live = i >= 0 && i < n;
+            const double rl = RAT[dir][j][live ? i : rt];
+            z = live ? -rl * z : z;
+            if (live) Z[j][i] = z;
+        }
+    }
+    __syncthreads();
+    for (int j = t >> 5; j < k; j += NT / 32) {
+        const int i = t & 31;
+        const double z = i < n ? Z[j][i] : 0.0;
+        const double s2 = sum32(z * z);
+        if (i < n) Z[j][i] = z / sqrt(s2);
+    }
+    __syncthreads();
+
+    // 4. residuals and orthogonality
+    const double rtol = 1e-11 * tn;
+    for (int e = t; e < k * 32; e += NT) {
+        const int j = e >> 5, i = e & 31;
+        if (i < n) {
+            double res = (Dg[i] - LAM[j]) * Z[j][i];
+            if (i > 0) res = fma(Ef[i - 1], Z[j][i - 1], res);
+            if (i + 1 < n) res = fma(Ef[i], Z[j][i + 1], res);
+            if (!(fabs(res) <= rtol)) bad = 1;
+        }
+    }
+    for (int e = t; e < k * k; e += NT) {
+        const int ja = e / k, jb = e % k;
+        double d = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxF; ++i) {
+            const double za = Z[ja][min(i, n - 1)], zb = Z[jb][min(i, n - 1)];
+            d = i < n ? fma(za, zb, d) : d;
+        }
+        M[ja][jb] = d;
+        if (ja != jb && !(fabs(d) <= 1e-10)) bad = 1;
+    }
+    __syncthreads();
+    if (bad) {  // uniform
+        jacobi_solve<NT>(g, F, vec, eval, 40);
+        return;
+    }
+    // z_j <- (z_j - sum_{a<j} M_aj z_a) / sqrt(1 - sum_{a<j} M_aj^2), into RAT[0] (free now)
+    for (int e = t; e < k * 32; e += NT) {
+        const int j = e >> 5, i = e & 31;
+        if (i < n) {
+            double z = Z[j][i], n2 = 1.0;
+            for (int ja = 0; ja < j; ++ja) {
+                z = fma(-M[ja][j], Z[ja][i], z);
+                n2 = fma(-M[ja][j], M[ja][j], n2);
+            }
+            RAT[0][j][i] = z / sqrt(n2);
+        }
+    }
+    __syncthreads();
+
+    // 5. v_j = Q z_j: this thread's four columns, then the row's eight threads
+    for (int j = 0; j < k; ++j) {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = l + 8 * u;
+            const double z = RAT[0][j][c < n ? c : 0];
+            v = c < n ? make_double2(fma(qm[u].x, z, v.x), fma(qm[u].y, z, v.y)) : v;
+        }
+        v.x = sum8(v.x);
+        v.y = sum8(v.y);
+        if (l == 0 && r < n) vec[r * F + j] = v;
+    }
+    if (t < k) eval[t] = LAM[t];
+}
+
 // pd[v] = |c_v|^2 - sum_{j<k} |sum_f c_v[f] vec[f][j]|^2  (float64), clamped at 0
 __global__ __launch_bounds__(256) void pd_kernel(const float2* __restrict__ y, int64_t V, int F, int k,
                                                  const double2* __restrict__ vec, float* __restrict__ pd) {
     __shared__ double2 sv[kMaxF * kMaxF];
-    for (int i = threadIdx.x; i < F * F; i += 256) sv[i] = vec[i];
+    for (int i = threadIdx.x; i < F * F; i += 256)
+        if (i % F < k) sv[i] = vec[i];  // the k columns the solver wrote
     __syncthreads();
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= V) return;
+    if (k >= F) {  // every component removed
+        pd[v] = 0.0f;
+        return;
+    }
     const float2* c = y + v * F;
     double e = 0.0;
     for (int f = 0; f < F; ++f) {
@@ -358,9 +755,12 @@ int power_doppler_impl(const void* y, int64_t V, int F, int n_clutter, float* pd
     double2* gram = part + (int64_t)nb * F * F;
     double2* vec = gram + (int64_t)F * F;
     double* eval = reinterpret_cast<double*>(vec + (int64_t)F * F);
-    hipLaunchKernelGGL(post::gram_partial_kernel, dim3(nb), dim3(256), 0, s, yy, V, F, chunk, part);
-    hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, gram);
-    hipLaunchKernelGGL(post::jacobi_kernel<256>, dim3(1), dim3(256), 0, s, gram, 1, F, vec, eval, 40);
+    // no filter (k = 0) keeps every voxel's energy and k = F removes all of it: no eigenvectors are needed
+    if (n_clutter > 0 && n_clutter < F) {
+        hipLaunchKernelGGL(post::gram_partial_kernel, dim3(nb), dim3(256), 0, s, yy, V, F, chunk, part);
+        hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, gram);
+        hipLaunchKernelGGL(post::eig_top_kernel, dim3(1), dim3(256), 0, s, gram, F, n_clutter, vec, eval);
+    }
     hipLaunchKernelGGL(post::pd_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, yy, V, F, n_clutter, vec,
                        pd);
     return post_launch_status("power_doppler launch failed");

@@ -37,7 +37,7 @@ def test_bmode_matches_oracle(V, F):
 
 
 @pytest.mark.parametrize("V,F,k", [(3000, 32, 0), (3000, 32, 1), (3000, 32, 5), (400, 7, 2), (400, 7, 7),
-                                   (2000, 16, 3), (50, 1, 1)])
+                                   (2000, 16, 3), (50, 1, 1), (3000, 29, 17), (3000, 32, 31), (500, 2, 1)])
 def test_power_doppler_matches_oracle_on_random_frames(V, F, k):
     r = np.random.default_rng(10 * V + F + k)
     # frames with a decaying spectrum of singular values so the k-subspace is well separated
@@ -47,6 +47,21 @@ def test_power_doppler_matches_oracle_on_random_frames(V, F, k):
     ref = P.power_doppler(y, k)
     scale = np.abs(ref).max() if k < F else (np.abs(y) ** 2).sum(1).max()
     assert np.abs(got - ref).max() <= 1e-6 * scale + 1e-30, (np.abs(got - ref).max(), scale)
+
+
+def test_power_doppler_with_repeated_largest_eigenvalues():
+    """Frames whose Gram matrix is exactly diagonal with the two largest eigenvalues equal: the top-2 subspace is
+    still unique (frames 0 and 1), but single eigenvectors are not, so the solver's orthogonality check sends it to
+    the Jacobi method; the result is the energy outside frames 0 and 1."""
+    V, F, k = 64, 12, 2
+    y = np.zeros((V, F), np.complex64)
+    for f in range(F):
+        y[f, f] = 2.0 if f < 2 else 1.0 - 0.05 * f
+    y[F:, :] = 0.0
+    got = _post().power_doppler(torch.as_tensor(y, device=DEV), k).cpu().numpy().astype(np.float64)
+    want = (np.abs(y[:, 2:]) ** 2).sum(1)
+    np.testing.assert_allclose(got, want, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(got, P.power_doppler(y, k), rtol=1e-6, atol=1e-9)
 
 
 def test_power_doppler_separates_tissue_from_blood():
