@@ -58,10 +58,9 @@ int64_t das_power_doppler_work(int64_t V, int F);
  * call allocates nothing and takes the same arguments minus the work buffer.
  * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
  * (concurrent streams or threads) race and must be serialised by the caller.
- * Up to 16 frames the result is bitwise that of das_power_doppler; with 17-32
- * frames the Gram matrix is summed over fewer, larger voxel chunks (float64
- * partial sums in another grouping).  The voxel count is not limited (chunks
- * grow with V).  DAS_ESHAPE unless V >= 1 and 1 <= F <= 32; DAS_EINVAL unless
+ * The result is bitwise that of das_power_doppler (the array holds the same
+ * voxel chunking for every frame count).  The voxel count is not limited
+ * (chunks grow with V).  DAS_ESHAPE unless V >= 1 and 1 <= F <= 32; DAS_EINVAL unless
  * 0 <= n_clutter <= F; DAS_EHIP if the array's address cannot be obtained. */
 int das_power_doppler_noalloc(const void *y, int64_t V, int F, int n_clutter, float *pd, void *stream);
 

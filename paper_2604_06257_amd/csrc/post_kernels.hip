@@ -72,50 +72,97 @@ __global__ void bmode_kernel(const float2* __restrict__ y, int64_t n, int F, con
     out[i] = db;
 }
 
-// part[i F + j][b] = sum over block b's voxel chunk of conj(y[v][i]) y[v][j]   (float64 complex, F <= 32)
+// Gram partial sums.  Block b sums conj(y[v][i]) y[v][j] over its chunk of voxels in float64, for the upper
+// triangle of 4 x 4 tiles of the 32 x 32 matrix (frames past F are zeros): 36 tiles, each owned by 7 threads that
+// take every 7th voxel of the chunk; a chunk is staged in LDS in float64 in sub-chunks of kGV voxels.  The 7
+// partial tiles are then added in thread order, and block b writes part[(i F + j) nb + b] for the entries of its
+// tiles (i <= j, and both triangles of the diagonal tiles): entry-major, so that the reduction reads contiguously.
+constexpr int kGV = 128;   // voxels per LDS stage
+constexpr int kGGrp = 7;   // voxel groups
+constexpr int kGTiles = 36;
 __global__ __launch_bounds__(256) void gram_partial_kernel(const float2* __restrict__ y, int64_t V, int F,
                                                            int64_t chunk, double2* __restrict__ part) {
-    __shared__ float2 tile[64 * kMaxF];
+    __shared__ double2 ys[kGV][kMaxF + 1];  // 67.6 KB; also the tiles' reduction area at the end
+    const int t = threadIdx.x;
+    const int grp = t / kGTiles, tile = t % kGTiles;
+    const bool busy = grp < kGGrp;
+    int bi = 0, bj = tile;  // tile -> (bi, bj), bi <= bj, row by row
+    while (bj >= 8 - bi) {
+        bj -= 8 - bi;
+        ++bi;
+    }
+    bj += bi;
+    double2 acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = make_double2(0.0, 0.0);
     const int64_t vb = (int64_t)blockIdx.x * chunk;
-    const int64_t ve = (vb + chunk < V) ? vb + chunk : V;
-    const int npair = F * F;
-    double2 acc[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = make_double2(0.0, 0.0);
-    for (int64_t v = vb; v < ve; v += 64) {
-        const int nv = (int)((ve - v < 64) ? ve - v : 64);
+    const int64_t ve = vb + chunk < V ? vb + chunk : V;
+    for (int64_t v0 = vb; v0 < ve; v0 += kGV) {
+        const int nv = (int)(ve - v0 < kGV ? ve - v0 : kGV);
         __syncthreads();
-        for (int i = threadIdx.x; i < nv * F; i += 256) tile[i] = y[v * F + i];
+        // lane f of a 32-lane half loads frame f of voxel (t / 32) + 8 i: consecutive lanes, consecutive samples
+        for (int v = t >> 5; v < kGV; v += 8) {
+            const int f = t & 31;
+            const float2 z = (v < nv && f < F) ? y[(v0 + v) * F + f] : make_float2(0.0f, 0.0f);
+            ys[v][f] = make_double2((double)z.x, (double)z.y);
+        }
         __syncthreads();
+        if (busy) {
+            for (int v = grp; v < nv; v += kGGrp) {
+                double2 ai[4], bq[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pr = threadIdx.x + 256 * r;
-            if (pr < npair) {
-                const int i = pr / F, j = pr % F;
-                double re = acc[r].x, im = acc[r].y;
-                for (int u = 0; u < nv; ++u) {
-                    const float2 a = tile[u * F + i], b = tile[u * F + j];
-                    // conj(a) * b
-                    re += (double)a.x * b.x + (double)a.y * b.y;
-                    im += (double)a.x * b.y - (double)a.y * b.x;
+                for (int p = 0; p < 4; ++p) {
+                    ai[p] = ys[v][4 * bi + p];
+                    bq[p] = ys[v][4 * bj + p];
                 }
-                acc[r] = make_double2(re, im);
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {  // conj(a) b
+                        acc[p][q].x = fma(ai[p].x, bq[q].x, fma(ai[p].y, bq[q].y, acc[p][q].x));
+                        acc[p][q].y = fma(ai[p].x, bq[q].y, fma(-ai[p].y, bq[q].x, acc[p][q].y));
+                    }
             }
         }
     }
+    __syncthreads();
+    double2* red = &ys[0][0];  // [grp][tile][16]
+    if (busy) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int pr = threadIdx.x + 256 * r;
-        if (pr < npair) part[(int64_t)pr * gridDim.x + blockIdx.x] = acc[r];  // entry-major: [pair][block]
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[(grp * kGTiles + tile) * 16 + p * 4 + q] = acc[p][q];
+    }
+    __syncthreads();
+    const int nb = gridDim.x;
+    for (int e = t; e < kGTiles * 16; e += 256) {
+        const int tl = e >> 4, pq = e & 15;
+        int ti = 0, tj = tl;
+        while (tj >= 8 - ti) {
+            tj -= 8 - ti;
+            ++ti;
+        }
+        tj += ti;
+        const int i = 4 * ti + (pq >> 2), j = 4 * tj + (pq & 3);
+        if (i < F && j < F) {
+            double2 sum = red[tl * 16 + pq];
+            for (int gg = 1; gg < kGGrp; ++gg) sum = make_double2(sum.x + red[(gg * kGTiles + tl) * 16 + pq].x,
+                                                                 sum.y + red[(gg * kGTiles + tl) * 16 + pq].y);
+            part[(int64_t)(i * F + j) * nb + blockIdx.x] = sum;
+        }
     }
 }
 
-// G[e] = sum_b part[e][b]: one wave per entry; lane l adds blocks l, l + 64, ... in order, then a fixed xor
-// butterfly over the 64 lanes (deterministic)
-__global__ __launch_bounds__(64) void gram_reduce_kernel(const double2* __restrict__ part, int nb,
+// G[i][j] = sum_b part[e][b] with e = (i, j) for i <= j, and the conjugate of entry (j, i) below the diagonal:
+// one wave per entry; lane l adds blocks l, l + 64, ... in order, then a fixed xor butterfly (deterministic)
+__global__ __launch_bounds__(64) void gram_reduce_kernel(const double2* __restrict__ part, int nb, int F,
                                                          double2* __restrict__ g) {
     const int e = blockIdx.x, lane = threadIdx.x;
-    const double2* src = part + (int64_t)e * nb;
+    const int i = e / F, j = e % F;
+    const bool lower = i > j;
+    const double2* src = part + (int64_t)(lower ? j * F + i : e) * nb;
     double re = 0.0, im = 0.0;
     for (int b = lane; b < nb; b += 64) {
         const double2 x = src[b];
@@ -126,7 +173,7 @@ __global__ __launch_bounds__(64) void gram_reduce_kernel(const double2* __restri
         re += __shfl_xor(re, o);
         im += __shfl_xor(im, o);
     }
-    if (lane == 0) g[e] = make_double2(re, im);
+    if (lane == 0) g[e] = make_double2(re, lower ? -im : im);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -665,36 +712,45 @@ __global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict_
     if (t < k) eval[t] = LAM[t];
 }
 
-// pd[v] = |c_v|^2 - sum_{j<k} |sum_f c_v[f] vec[f][j]|^2  (float64), clamped at 0
+// pd[v] = |c_v|^2 - sum_{j<k} |sum_f c_v[f] vec[f][j]|^2  (float64), clamped at 0; k = F gives 0.  A block
+// stages kPV voxel rows through LDS (coalesced loads), then one thread per voxel.
+constexpr int kPV = 128;
 __global__ __launch_bounds__(256) void pd_kernel(const float2* __restrict__ y, int64_t V, int F, int k,
                                                  const double2* __restrict__ vec, float* __restrict__ pd) {
     __shared__ double2 sv[kMaxF * kMaxF];
-    for (int i = threadIdx.x; i < F * F; i += 256)
+    __shared__ float2 ys[kPV][kMaxF + 1];
+    const int t = threadIdx.x;
+    const int64_t v0 = (int64_t)blockIdx.x * kPV;
+    const int nv = (int)(V - v0 < kPV ? V - v0 : kPV);
+    for (int i = t; i < F * F; i += 256)
         if (i % F < k) sv[i] = vec[i];  // the k columns the solver wrote
+    if (F == kMaxF) {
+        for (int v = t >> 5; v < nv; v += 8) ys[v][t & 31] = y[(v0 + v) * kMaxF + (t & 31)];
+    } else {
+        for (int i = t; i < nv * F; i += 256) ys[i / F][i % F] = y[v0 * F + i];
+    }
     __syncthreads();
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (v >= V) return;
+    if (t >= nv) return;
     if (k >= F) {  // every component removed
-        pd[v] = 0.0f;
+        pd[v0 + t] = 0.0f;
         return;
     }
-    const float2* c = y + v * F;
     double e = 0.0;
     for (int f = 0; f < F; ++f) {
-        const float2 z = c[f];
-        e += (double)z.x * z.x + (double)z.y * z.y;
+        const float2 z = ys[t][f];
+        e = fma((double)z.x, (double)z.x, fma((double)z.y, (double)z.y, e));
     }
     for (int j = 0; j < k; ++j) {
         double re = 0.0, im = 0.0;
         for (int f = 0; f < F; ++f) {
-            const float2 z = c[f];
+            const float2 z = ys[t][f];
             const double2 w = sv[f * F + j];
-            re += z.x * w.x - z.y * w.y;
-            im += z.x * w.y + z.y * w.x;
+            re = fma((double)z.x, w.x, fma(-(double)z.y, w.y, re));
+            im = fma((double)z.x, w.y, fma((double)z.y, w.x, im));
         }
         e -= re * re + im * im;
     }
-    pd[v] = (float)(e > 0.0 ? e : 0.0);
+    pd[v0 + t] = (float)(e > 0.0 ? e : 0.0);
 }
 
 }  // namespace post
@@ -708,10 +764,11 @@ int pfail(int st, const char* msg) {
 int post_launch_status(const char* what) {
     return hipGetLastError() == hipSuccess ? DAS_OK : pfail(DAS_EHIP, what);
 }
-// voxels per Gram partial block: at most max_blocks blocks (2048 fill the chip), at least one 64-voxel tile each
-int64_t gram_chunk(int64_t V, int64_t max_blocks = 2048) {
+// Gram partial blocks: at most kGramBlocks (two per CU), each at least one 128-voxel LDS stage
+constexpr int64_t kGramBlocks = 512;
+int64_t gram_chunk(int64_t V, int64_t max_blocks = kGramBlocks) {
     const int64_t c = (V + max_blocks - 1) / max_blocks;
-    return c < 64 ? 64 : c;
+    return c < post::kGV ? post::kGV : c;
 }
 
 // Work layout of Power Doppler in double2 units: nb partial Gram matrices, their sum, the eigenvectors, then the
@@ -719,9 +776,9 @@ int64_t gram_chunk(int64_t V, int64_t max_blocks = 2048) {
 int64_t pd_work2(int64_t nb, int F) { return nb * F * F + 2 * (int64_t)F * F + (F + 1) / 2; }
 
 // Allocation-free Power Doppler: its work lives in this fixed device array (one per GPU, kept until the process
-// ends).  Size: the work of 2048 partial blocks at 16 frames, so that up to 16 frames the voxel chunking is the
-// same as with a caller's buffer; 17-32 frames use fewer, larger chunks.
-constexpr int64_t kScratch2 = 2048 * 16 * 16 + 2 * 32 * 32 + 16;  // double2 entries (8.03 MiB)
+// ends).  Size: the work of kGramBlocks partial blocks at 32 frames, so that the voxel chunking (and the result)
+// is that of a call with a caller's buffer for every frame count.
+constexpr int64_t kScratch2 = kGramBlocks * 32 * 32 + 2 * 32 * 32 + 16;  // double2 entries (8.03 MiB)
 static __device__ __align__(256) double2 scratch[kScratch2];
 
 constexpr int kMaxDevices = 64;
@@ -758,10 +815,11 @@ int power_doppler_impl(const void* y, int64_t V, int F, int n_clutter, float* pd
     // no filter (k = 0) keeps every voxel's energy and k = F removes all of it: no eigenvectors are needed
     if (n_clutter > 0 && n_clutter < F) {
         hipLaunchKernelGGL(post::gram_partial_kernel, dim3(nb), dim3(256), 0, s, yy, V, F, chunk, part);
-        hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, gram);
+        hipLaunchKernelGGL(post::gram_reduce_kernel, dim3((unsigned)(F * F)), dim3(64), 0, s, part, nb, F, gram);
         hipLaunchKernelGGL(post::eig_top_kernel, dim3(1), dim3(256), 0, s, gram, F, n_clutter, vec, eval);
     }
-    hipLaunchKernelGGL(post::pd_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, yy, V, F, n_clutter, vec,
+    hipLaunchKernelGGL(post::pd_kernel, dim3((unsigned)((V + post::kPV - 1) / post::kPV)), dim3(256), 0, s, yy, V, F,
+                       n_clutter, vec,
                        pd);
     return post_launch_status("power_doppler launch failed");
 }
@@ -809,7 +867,7 @@ int das_power_doppler(const void* y, int64_t V, int F, int n_clutter, float* pd,
     if (n_clutter < 0 || n_clutter > F) return pfail(DAS_EINVAL, "power_doppler: need 0 <= n_clutter <= F");
     if (work_doubles < das_power_doppler_work(V, F)) return pfail(DAS_ESHAPE, "power_doppler: work buffer too small");
     if (reinterpret_cast<uintptr_t>(work) % 16 != 0) return pfail(DAS_EALIGN, "power_doppler: work must be 16-byte aligned");
-    return power_doppler_impl(y, V, F, n_clutter, pd, reinterpret_cast<double2*>(work), 2048,
+    return power_doppler_impl(y, V, F, n_clutter, pd, reinterpret_cast<double2*>(work), kGramBlocks,
                               reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -818,9 +876,9 @@ int das_power_doppler_noalloc(const void* y, int64_t V, int F, int n_clutter, fl
     if (V < 1 || F < 1 || F > post::kMaxF)
         return pfail(DAS_ESHAPE, "power_doppler_noalloc: need V >= 1 and 1 <= F <= 32");
     if (n_clutter < 0 || n_clutter > F) return pfail(DAS_EINVAL, "power_doppler_noalloc: need 0 <= n_clutter <= F");
-    // the most Gram partial blocks the scratch array holds at F frames (F <= 32 always leaves room for 500)
+    // the most Gram partial blocks the scratch array holds at F frames (at least kGramBlocks for F <= 32)
     const int64_t fit = (kScratch2 - pd_work2(0, F)) / ((int64_t)F * F);
-    const int64_t max_blocks = fit < 2048 ? fit : 2048;
+    const int64_t max_blocks = fit < kGramBlocks ? fit : kGramBlocks;
     if (pd_work2((V + gram_chunk(V, max_blocks) - 1) / gram_chunk(V, max_blocks), F) > kScratch2)
         return pfail(DAS_ESHAPE, "power_doppler_noalloc: work exceeds the 8 MiB scratch array");
     double2* work = nullptr;

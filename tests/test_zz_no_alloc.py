@@ -1,9 +1,8 @@
 """das_power_doppler_noalloc (the allocation-free Power Doppler) against das_power_doppler, through the C ABI.
 
 Two calls in a row on the same GPU, the second with a smaller input, each compared with das_power_doppler on
-the same frames: bitwise up to 16 frames (same voxel chunks), and within 1e-6 of the peak with 17-32 frames
-(the Gram matrix summed in float64 over another grouping of voxel chunks), the bar of the Power Doppler
-tests.  The scratch array keeps the first call's contents: the second call must not depend on them.
+the same frames: bitwise, since the scratch array holds the same voxel chunking as a caller's work buffer for
+every frame count.  The scratch array keeps the first call's contents: the second call must not depend on them.
 """
 
 import ctypes
@@ -56,10 +55,7 @@ def test_power_doppler_noalloc_matches_the_work_buffer_entry_point(calls):
         torch.cuda.synchronize()
         g, r = got.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
         assert np.isfinite(g).all()
-        if F <= 16:
-            np.testing.assert_array_equal(g, r)
-        else:
-            assert np.abs(g - r).max() <= 1e-6 * np.abs(r).max(), (V, F, k, np.abs(g - r).max(), np.abs(r).max())
+        np.testing.assert_array_equal(g, r)
 
 
 def test_power_doppler_noalloc_rejects_bad_arguments():
