@@ -384,6 +384,75 @@ __device__ __forceinline__ void sturm_counts(const double (&d)[kMaxF], const dou
     }
 }
 
+constexpr int kFastK = 4, kFastIters = 24;  // fast path of the top-k solver: largest k, iterations
+
+// One round of the top-k solver's fast path, by the 64 lanes of one wave (lanes 0-31 hold rows 0-31, lanes 32-63
+// repeat them; their results are not used): X (orthonormal, xs) and Y = G X (ys) give H = X^H Y and
+// R = Y - X H.  If the certificate holds, X is written out as the eigenvector basis (vec[f][j]) with eval[j] =
+// H_jj and state = 1; otherwise xs <- an orthonormal basis of Y (modified Gram-Schmidt), and state = 2 when a
+// column vanishes or this was the last round.
+template <int K>
+__device__ void fast_check(double2 (*xs)[kMaxF], double2 (*ys)[kMaxF], int n, int F, double trg, bool last,
+                           double2* __restrict__ vec, double* __restrict__ eval, int& state) {
+    const int lane = threadIdx.x & 63, rr = lane & 31;
+    double2 x[K], y[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        x[j] = xs[j][rr];
+        y[j] = ys[j][rr];
+    }
+    double2 h[K][K];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double2 c = cmul(cconj(x[i]), y[j]);
+            h[i][j] = make_double2(sum32(c.x), sum32(c.y));
+        }
+    double r2 = 0.0, trh = 0.0, alo = 1.0 / 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        double2 rj = y[j];
+#pragma unroll
+        for (int i = 0; i < K; ++i) rj = csub(rj, cmul(x[i], h[i][j]));
+        r2 = fma(rj.x, rj.x, fma(rj.y, rj.y, r2));
+        trh += h[j][j].x;
+        double off = 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i != j) off += sqrt(fma(h[i][j].x, h[i][j].x, h[i][j].y * h[i][j].y));
+        alo = fmin(alo, h[j][j].x - off);
+    }
+    const double rn = sqrt(sum32(r2));
+    const double delta = alo - (trg - trh) - 1e-13 * fabs(trg);
+    if (delta > 0.0 && rn <= 1e-12 * delta) {
+        if (lane < n) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) vec[lane * F + j] = x[j];
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) eval[j] = h[j][j].x;
+            state = 1;
+        }
+        return;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            const double2 c = cmul(cconj(y[i]), y[j]);
+            y[j] = csub(y[j], cmul(y[i], make_double2(sum32(c.x), sum32(c.y))));
+        }
+        const double nr = sum32(fma(y[j].x, y[j].x, y[j].y * y[j].y));
+        ok = ok && nr > 1e-280 && nr <= 1.7e308;
+        y[j] = cscale(y[j], ok ? 1.0 / sqrt(nr) : 0.0);
+        if (lane < 32) xs[j][lane] = lane < n ? y[j] : make_double2(0.0, 0.0);
+    }
+    if (lane == 0 && (!ok || last)) state = 2;
+}
+
 // 1 / x from the hardware reciprocal and two Newton steps (within an ulp or so; x finite and nonzero)
 __device__ __forceinline__ double rcp_d(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -405,6 +474,13 @@ __device__ __forceinline__ double rcp_d(double x) {
 //   4. checks: every residual |(T - lambda) z|_i <= 1e-11 |T| and every |z_a . z_b| <= 1e-10; then one classical
 //      Gram-Schmidt pass against the vectors of larger eigenvalues;
 //   5. v = Q z.
+// Before that, for k <= 4, a fast path: subspace iteration X <- orth(G X) from the unit vectors of the k largest
+// diagonal entries, accepted as soon as the sin-theta bound certifies it: with H = X^H G X and R = G X - X H,
+// the clutter subspace is within ||R||_F / delta of span X, where delta = (a Gershgorin lower bound of the
+// eigenvalues of H) - (trace G - trace H, an upper bound of the (k+1)-th eigenvalue of the positive
+// semidefinite G); span X is used when ||R||_F <= 1e-12 delta (the Power Doppler needs the subspace only).
+// It serves spectra whose k largest eigenvalues hold most of the energy (tissue clutter); other spectra, or 24
+// iterations without a certificate, go on to steps 1-5.
 // A spectrum that fails a check (eigenvalues repeated among the k largest, non-finite input) takes the Jacobi
 // solver instead, for the same output.  Every reduction is in a fixed order: the result is deterministic.
 __global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict__ g, int F, int k,
@@ -425,6 +501,7 @@ __global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict_
     __shared__ double M[kMaxF][kMaxF + 1];       // Z Z^T
     __shared__ int TW[kMaxF];
     __shared__ int bad;
+    __shared__ double TRG;
     const int n = F, t = threadIdx.x;
     const int r = t >> 3, l = t & 7;  // this thread's row and first column
     double2 a[4], qm[4];              // G (being reduced) and Q at (r, l + 8u)
@@ -444,6 +521,61 @@ __global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict_
     if (t == 0) {
         bad = 0;
         HVp[0] = TVC[0] = PVp[0] = CPp[0] = make_double2(0.0, 0.0);
+    }
+
+    // 0. fast path (see above); G in registers is left as it was for steps 1-5
+    if (k <= kFastK) {
+        __shared__ double2 XS[kFastK][kMaxF], YS[kFastK][kMaxF];
+        __shared__ int fast_state;  // 0 iterating, 1 certified, 2 given up
+        const int lane = t & 63;
+        if (t < 64) {
+            // trace and the start vectors e_m for the k largest diagonal entries (ties to the lower index)
+            double dg = lane < n ? g[lane * (n + 1)].x : -1.0 / 0.0;
+            const double tr = sum32(lane < 32 && lane < n ? g[lane * (n + 1)].x : 0.0);
+            if (lane == 0) TRG = tr;
+            for (int j = 0; j < k; ++j) {
+                double bv = lane < 32 ? dg : -1.0 / 0.0;
+                int bi = lane;
+                for (int o = 16; o > 0; o >>= 1) {
+                    const double ov = __shfl_xor(bv, o);
+                    const int oi = __shfl_xor(bi, o);
+                    if (ov > bv || (ov == bv && oi < bi)) {
+                        bv = ov;
+                        bi = oi;
+                    }
+                }
+                if (lane < 32) XS[j][lane] = make_double2(lane == bi ? 1.0 : 0.0, 0.0);
+                if (lane == bi) dg = -1.0 / 0.0;
+            }
+            if (lane == 0) fast_state = 0;
+        }
+        for (int i = t; i < kFastK * kMaxF; i += NT) YS[i / kMaxF][i % kMaxF] = make_double2(0.0, 0.0);
+        __syncthreads();
+        for (int it = 0; it < kFastIters; ++it) {
+            // Y = G X: this thread's four columns, then the row's eight threads
+            for (int j = 0; j < k; ++j) {
+                double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) y = cadd(y, cmul(a[u], XS[j][l + 8 * u]));
+                y.x = sum8(y.x);
+                y.y = sum8(y.y);
+                if (l == 0 && r < n) YS[j][r] = y;
+            }
+            __syncthreads();
+            if (t < 64) {
+                const bool last = it + 1 == kFastIters;
+                switch (k) {
+                    case 1: fast_check<1>(XS, YS, n, F, TRG, last, vec, eval, fast_state); break;
+                    case 2: fast_check<2>(XS, YS, n, F, TRG, last, vec, eval, fast_state); break;
+                    case 3: fast_check<3>(XS, YS, n, F, TRG, last, vec, eval, fast_state); break;
+                    default: fast_check<4>(XS, YS, n, F, TRG, last, vec, eval, fast_state); break;
+                }
+            }
+            __syncthreads();
+            const int st = fast_state;
+            if (st == 1) return;
+            if (st == 2) break;
+        }
     }
     __syncthreads();
 
