@@ -303,6 +303,69 @@ def hbm_report(T, E, S, F, V, info, ms, traffic):
     return rep
 
 
+def unet_forward_report(steps, warmup, dims=(96, 96, 96)):
+    """Forward pass of the learned-compounding U-Net (random weights, random bfloat16 input) on a dims grid: the
+    whole forward, then each convolution alone (HIP events around each call, median over the steps), with its
+    FLOPs (2 x 27 x Cin x Cout per voxel) as a share of the 2.5 PFLOP/s dense BF16 MFMA peak."""
+    import torch
+    from paper_2604_06257_amd import learn
+    U = learn.UNet(dims)
+    V = dims[0] * dims[1] * dims[2]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = torch.randn((V, U.cin), device="cuda", generator=g).to(torch.bfloat16)
+
+    def timed_forward(n):
+        for _ in range(warmup):
+            U.forward(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            U.forward(x)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    fw_ms = timed_forward(steps)
+    orig, rec = learn.conv3d, []
+
+    def conv_timed(xx, w, bias, out, d, **kw):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = orig(xx, w, bias, out, d, **kw)
+        e1.record()
+        rec.append((tuple(d), learn._whole(xx).c, learn._whole(out).c, e0, e1))
+        return r
+
+    learn.conv3d = conv_timed
+    try:
+        for _ in range(warmup):
+            U.forward(x)
+        torch.cuda.synchronize()
+        rec.clear()
+        for _ in range(steps):
+            U.forward(x)
+        torch.cuda.synchronize()
+    finally:
+        learn.conv3d = orig
+    per = len(rec) // steps
+    layers, flops = [], 0
+    for i, (name, _, _) in enumerate(learn.layer_shapes(U.cin, U.chans, U.cout)[:per]):
+        d, ci, co = rec[i][:3]
+        ts = sorted(rec[i + j * per][3].elapsed_time(rec[i + j * per][4]) for j in range(steps))
+        us = 1e3 * ts[steps // 2]
+        fl = 2 * 27 * ci * co * d[0] * d[1] * d[2]
+        flops += fl
+        layers.append({"layer": name, "dims": list(d), "cin": ci, "cout": co, "us": us,
+                       "tflops": fl / us / 1e6, "frac_bf16_peak": fl / us / 1e6 / 2500.0})
+    return {"unet_forward": {"dims": list(dims), "gflop": flops / 1e9, "ms": fw_ms,
+                             "tflops": flops / fw_ms / 1e9, "frac_bf16_peak": flops / fw_ms / 1e9 / 2500.0,
+                             "steps": steps, "layers": layers,
+                             "note": "random weights and input; forward only; the peak is the dense BF16 MFMA "
+                                     "2.5 PFLOP/s"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,7 +382,12 @@ def main():
                     help="also time B-mode and Power Doppler (SVD clutter filter, rank 1) on the beamformed frames")
     ap.add_argument("--sweep", choices=("voxels", "elements", "frames"), default=None,
                     help="print one JSON line per size along this axis instead of the benchmark line")
+    ap.add_argument("--unet", action="store_true",
+                    help="print the learned-compounding U-Net forward timing at 96^3 (one JSON line) instead")
     args = ap.parse_args()
+    if args.unet:
+        print(json.dumps(unet_forward_report(max(5, min(args.steps, 50)), max(2, min(args.warmup, 5)))))
+        return
     if args.sweep:
         scaling_sweep(args.sweep, args.steps, args.warmup)
         return
