@@ -303,6 +303,23 @@ def hbm_report(T, E, S, F, V, info, ms, traffic):
     return rep
 
 
+C5_WEIGHTS = os.path.join(ROOT, "paper_2604_06257_amd", "weights", "unet_c5.npz")
+
+
+def c5_report(n_test=20):
+    """Learned compounding (c5: 96^3 voxels, 32 x 32 elements, 11 plane waves, 1 frame) with the stored weights of
+    the network trained on 1800 phantoms, on n_test freshly generated held-out phantoms (the training run's test
+    seeds): NRMSE against the 11-angle compound of (11/3) x the 3-angle sum and of the network, the 11-angle DAS
+    time and the learned path's (3-angle per-transmit DAS + features + network)."""
+    from paper_2604_06257_amd import train_compound
+    r = train_compound.evaluate_checkpoint(C5_WEIGHTS, n_test=n_test)
+    return {"workload": "c5: learned compounding of 3 of 11 plane waves (-10, 0, +10 deg), 96^3 grid, "
+                        "32 x 32 array, 1 frame; stored weights, held-out phantoms generated here",
+            "n_test": r["n_test"], "test_phantom_seeds": r["test_phantom_seeds"],
+            "nrmse_db_vs_11_angle": r["nrmse_db_vs_full_compound"], "gain_db": r["gain_db"],
+            "ms": r["ms"], "speedup_vs_11_angle_das": r["speedup"], "trained": r["trained"]}
+
+
 def unet_forward_report(steps, warmup, dims=(96, 96, 96)):
     """Forward pass of the learned-compounding U-Net (random weights, random bfloat16 input) on a dims grid: the
     whole forward, then each convolution alone (HIP events around each call, median over the steps), with its
@@ -375,6 +392,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP16 / BF16 IQ timings")
     ap.add_argument("--no-c3", action="store_true", help="skip the c3 sub-object")
+    ap.add_argument("--no-c5", action="store_true", help="skip the c5 (learned compounding) sub-object")
     ap.add_argument("--cpu-voxels", type=int, default=None, help="voxels in the oracle sample (default: all)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a torch copy of this many GiB (for HBM counter calibration)")
@@ -490,6 +508,9 @@ def main():
         result["iq16_variants"] = var
     if not args.no_c3 and args.workload != "c3":
         result["c3"] = c3_report(max(5, args.steps // 10), max(2, args.warmup // 4), torch, das, oracle)
+        torch.cuda.empty_cache()
+    if not args.no_c5 and args.workload == "c2":
+        result["c5"] = c5_report()
         torch.cuda.empty_cache()
     if args.post:
         from paper_2604_06257_amd import post

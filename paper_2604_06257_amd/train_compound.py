@@ -215,8 +215,58 @@ def run(args, log=print):
            "net_tflops_forward": round(lc.net.flops_forward() / (times["network"] * 1e-3) / 1e12, 2),
            "seconds": {"data": round(t_data, 1), "train": round(t_train, 1)},
            "ms_per_train_step": round(1e3 * t_train / max(1, args.steps), 3)}
+    if getattr(args, "save_weights", None):
+        save_weights(lc.net, args.save_weights, res)
     lc.close()
     return res
+
+
+def save_weights(net, path, summary=None):
+    """The network's FP32 master weights as a NumPy archive (no pickled objects): arrays '<layer>.w' [Cout, 27,
+    Cin] and '<layer>.b' [Cout], plus 'summary' (the training record as JSON text)."""
+    arrays = {}
+    for name, (w, b) in net.get_params().items():
+        arrays[name + ".w"] = w
+        arrays[name + ".b"] = b
+    arrays["summary"] = np.array(json.dumps(summary or {}))
+    with open(path, "wb") as f:
+        np.savez(f, **arrays)
+
+
+def load_weights(net, path):
+    """Weights written by save_weights into net (loaded without unpickling); returns the training record."""
+    with np.load(path, allow_pickle=False) as z:
+        net.set_params({name: (z[name + ".w"], z[name + ".b"]) for name, _, _ in net.shapes})
+        return json.loads(str(z["summary"]))
+
+
+def evaluate_checkpoint(path, n_test=20, geometry_name="c5", log=None):
+    """The learned path with stored weights on freshly generated held-out phantoms (the test seeds of the training
+    run that wrote them): NRMSE of (11/3) x the 3-angle sum and of the network against the 11-angle compound, and
+    the timing of both paths."""
+    geo = geometry(geometry_name)
+    p = geo["params"]
+    dev = torch.device("cuda")
+    elem = torch.as_tensor(np.ascontiguousarray(geo["elem"], dtype=np.float32), device=dev)
+    vox = torch.as_tensor(np.ascontiguousarray(geo["vox"], dtype=np.float32), device=dev)
+    tx = _das.tx_plane_wave(vox, geo["angles"], p["c"])
+    T, E, V = geo["angles"].shape[0], elem.shape[0], vox.shape[0]
+    params = _das.Params(T, E, p["n_samples"], 1, V, p["c"], p["fs"], p["fd"], p["t0"], p["f_number"],
+                         p["tukey_alpha"])
+    lc = LearnedCompounding(params, elem, vox, tx, geo["dims"], geo["input_idx"])
+    try:
+        rec = load_weights(lc.net, path)
+        first = int(rec.get("n_train", 0)) + int(rec.get("n_val", 0))
+        test = Dataset(lc, geo, n_test, first=first, log=log)
+        base_db, net_db = evaluate(lc, test)
+        times = time_paths(lc, geo)
+    finally:
+        lc.close()
+    return {"geometry": geometry_name, "dims": list(geo["dims"]), "n_angles": T, "n_test": n_test,
+            "test_phantom_seeds": [first, first + n_test - 1],
+            "nrmse_db_vs_full_compound": {"scaled_input_sum": base_db, "network": net_db},
+            "gain_db": base_db - net_db, "ms": times, "speedup": times["full_das"] / times["learned_total"],
+            "trained": {k: rec.get(k) for k in ("n_train", "n_val", "steps", "checkpoint_step", "test_nrmse_db")}}
 
 
 def main(argv=None):
@@ -231,6 +281,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--log-every", type=int, default=500)
     ap.add_argument("--out", default=None, help="write the JSON summary here")
+    ap.add_argument("--save-weights", default=None, help="write the trained weights (NumPy archive) here")
     args = ap.parse_args(argv)
 
     def log(msg):
