@@ -111,6 +111,32 @@ def test_conv3d_slices_mask_and_flip_match_oracle():
     np.testing.assert_allclose(host(dx).reshape(ref_dx.shape), ref_dx, rtol=2e-5, atol=2e-5 * np.abs(ref_dx).max())
 
 
+def test_conv3d_unaligned_output_and_mask_slices():
+    """Output and mask slices whose channel offset or row stride is not a multiple of 16 bytes take the
+    epilogue's element-by-element stores: the same values as the oracle (float32 and bfloat16 output)."""
+    L = _learn()
+    D, H, W, cin, cout = 3, 9, 10, 16, 16
+    r = np.random.default_rng(11)
+    x = bf16_round(r.standard_normal((D, H, W, cin)))
+    w = bf16_round(r.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    b = r.standard_normal(cout).astype(np.float32).astype(np.float64)
+    maskv = bf16_round(np.maximum(r.standard_normal((D, H, W, 21)), 0.0))  # stride 21, offset 3
+    ref = np.maximum(U.conv3d(x, w, b), 0.0) * (maskv[..., 3:19] > 0)
+    wd, bd = to_dev_bf16(w.reshape(cout, -1)).reshape(-1), torch.as_tensor(b, dtype=torch.float32, device=DEV)
+    out = torch.full((D * H * W, 19), -5.0, dtype=torch.float32, device=DEV)  # float32: stride 19, offset 2
+    L.conv3d(to_dev_bf16(x), wd, bd, L.Slice(out, 2, cout), (D, H, W), relu=True,
+             mask=L.Slice(to_dev_bf16(maskv), 3, cout))
+    got = host(out).reshape(D, H, W, 19)
+    np.testing.assert_allclose(got[..., 2:18], ref, rtol=2e-5, atol=2e-5 * np.abs(ref).max())
+    assert np.all(got[..., :2] == -5.0) and np.all(got[..., 18:] == -5.0)
+    outb = torch.zeros((D * H * W, 20), dtype=torch.bfloat16, device=DEV)  # bfloat16: offset 4 (8 bytes)
+    L.conv3d(to_dev_bf16(x), wd, bd, L.Slice(outb, 4, cout), (D, H, W), relu=True,
+             mask=L.Slice(to_dev_bf16(maskv), 3, cout))
+    gb = host(outb).reshape(D, H, W, 20)
+    np.testing.assert_allclose(gb[..., 4:20], bf16_round(got[..., 2:18]), rtol=1e-2, atol=1e-6 * np.abs(ref).max())
+    assert np.all(gb[..., :4] == 0.0)
+
+
 @pytest.mark.parametrize("D,H,W,cin,cout,chunk", [(4, 4, 4, 8, 16, 32), (5, 7, 9, 16, 32, 64),
                                                   (6, 6, 6, 48, 16, 32), (4, 4, 4, 112, 48, 96),
                                                   (8, 8, 8, 64, 64, 512)])
