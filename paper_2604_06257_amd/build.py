@@ -31,18 +31,23 @@ def _run(cmd):
 
 
 def build(verbose=False):
-    """Compile all sources and link libdas.so; returns its path."""
+    """Compile all sources (concurrently, one hipcc per source) and link libdas.so; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        out = _run([HIPCC] + COMMON + DEVICE_FLAGS + lang + ["-c", path, "-o", obj])
-        if verbose and out.strip():
-            print(out)
-        objs.append(obj)
+        jobs.append(([HIPCC] + COMMON + DEVICE_FLAGS + lang + ["-c", path, "-o", obj], obj))
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        outs = list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [obj for _, obj in jobs]
+    if verbose:
+        for out in outs:
+            if out.strip():
+                print(out)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -49,7 +49,7 @@ constexpr int kMaxNT = 8;  // up to 128 output channels per launch
 //
 // With several channel chunks and DB the halo is double-buffered: the next chunk's loads are issued before the
 // current chunk's MFMAs and written to the other buffer after them, one barrier per chunk (used for launches with
-// few workgroups; elsewhere the second buffer's LDS would cost more occupancy than it hides latency).
+// few workgroups, in the 1 x 1 shape; elsewhere the second buffer's LDS costs more occupancy than it hides).
 //
 // Epilogue: bias, ReLU, then the tile goes through LDS as float [voxel][channel], and each thread writes 8
 // channels of a voxel (one 16-byte store, two for float output) after the optional mask; with `vec` = 0
@@ -751,16 +751,20 @@ void launch_conv_t(int ngroups, int out_f32, const learn::Vol& vol, hipStream_t 
     const int ea = out_f32 ? 4 : 8;
     const bool vec = reinterpret_cast<uintptr_t>(out) % 16 == 0 && out_stride % ea == 0 && out_coff % ea == 0 &&
                      (!mk || (reinterpret_cast<uintptr_t>(mk) % 16 == 0 && mask_stride % 8 == 0 && mask_coff % 8 == 0));
-    // double-buffered halo only for small launches (few workgroups: latency-bound); on large ones the second
-    // buffer costs occupancy (d0a at 96^3: 84 -> 94 us; the 24^3 and 12^3 layers gain ~1 us each)
-    if (cin > CC && (int64_t)nb * ngroups <= 768)
-        hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC, true>), dim3(nb, ngroups), dim3(256), 0, s, x, in_stride,
-                           in_coff, w, bias, out, out_stride, out_coff, out_f32, mk, mask_stride, mask_coff, vol, cin,
-                           flip, relu, (int)vec);
-    else
-        hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC, false>), dim3(nb, ngroups), dim3(256), 0, s, x, in_stride,
-                           in_coff, w, bias, out, out_stride, out_coff, out_f32, mk, mask_stride, mask_coff, vol, cin,
-                           flip, relu, (int)vec);
+    // double-buffered halo only for small launches (few workgroups: latency-bound), which take the 1 x 1 shape;
+    // on large ones the second buffer costs occupancy (d0a at 96^3: 84 -> 94 us; the 24^3 and 12^3 layers gain
+    // ~1 us each).  Other shapes are not instantiated double-buffered (compile time).
+    if constexpr (MT == 1 && NT == 1) {
+        if (cin > CC && (int64_t)nb * ngroups <= 768) {
+            hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC, true>), dim3(nb, ngroups), dim3(256), 0, s, x,
+                               in_stride, in_coff, w, bias, out, out_stride, out_coff, out_f32, mk, mask_stride,
+                               mask_coff, vol, cin, flip, relu, (int)vec);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((learn::conv3d_kernel<MT, NT, CC, false>), dim3(nb, ngroups), dim3(256), 0, s, x, in_stride,
+                       in_coff, w, bias, out, out_stride, out_coff, out_f32, mk, mask_stride, mask_coff, vol, cin,
+                       flip, relu, (int)vec);
 }
 
 template <int MT, int NT>
