@@ -252,7 +252,7 @@ __device__ void jacobi_solve(const double2* __restrict__ g, int F, double2* __re
                 // rotate unless |a_pq| is negligible against its diagonal pair (|a_pq| <= 1e-15 sqrt(a_pp a_qq))
                 // or at the rounding floor of the whole matrix (|a_pq| <= 1e-16 trace G)
                 if (q < F && b2 > floor2 && b2 > 1e-30 * fabs(app * aqq)) {
-                    rotated = 1;
+                    atomicOr(&rotated, 1);
                     const double rb = rsqrt(b2);                       // 1 / |a_pq|
                     const double e_re = apq.x * rb, e_im = -apq.y * rb;  // e = exp(-i arg a_pq)
                     const double tau = 0.5 * (aqq - app) * rb;
@@ -795,7 +795,7 @@ __global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict_
             double res = (Dg[i] - LAM[j]) * Z[j][i];
             if (i > 0) res = fma(Ef[i - 1], Z[j][i - 1], res);
             if (i + 1 < n) res = fma(Ef[i], Z[j][i + 1], res);
-            if (!(fabs(res) <= rtol)) bad = 1;
+            if (!(fabs(res) <= rtol)) atomicOr(&bad, 1);
         }
     }
     for (int e = t; e < k * k; e += NT) {
@@ -807,7 +807,7 @@ __global__ __launch_bounds__(256) void eig_top_kernel(const double2* __restrict_
             d = i < n ? fma(za, zb, d) : d;
         }
         M[ja][jb] = d;
-        if (ja != jb && !(fabs(d) <= 1e-10)) bad = 1;
+        if (ja != jb && !(fabs(d) <= 1e-10)) atomicOr(&bad, 1);
     }
     __syncthreads();
     if (bad) {  // uniform
