@@ -434,13 +434,18 @@ int das_plan_create(das_plan** out, const das_params* p, const float* elem_xyz, 
         if (elem[3 * k + 2] != elem[2]) kp.planar = 0;
     kp.z0 = kp.planar ? (double)elem[2] : 0.0;
 
-    const std::vector<double> elemd(elem.begin(), elem.end());
+    // element coordinates, then a 64-byte zero row (16-byte aligned) that the beamforming kernel reads in place of
+    // samples outside a record
+    const size_t zoff = (3 * (size_t)E + 1) / 2 * 2;
+    std::vector<double> elemd(zoff + 8, 0.0);
+    for (int64_t k = 0; k < 3 * E; ++k) elemd[(size_t)k] = (double)elem[k];
     unsigned long long* counts = nullptr;
     unsigned long long hc[3] = {0, 0, 0};
     if ((e = upload(&d.vx, vx, s)) != hipSuccess || (e = upload(&d.vy, vy, s)) != hipSuccess ||
         (e = upload(&d.vz, vz, s)) != hipSuccess || (e = upload(&d.tx, txs, s)) != hipSuccess ||
         (e = upload(&d.slot_vox, tl.slot_to_vox, s)) != hipSuccess || (e = upload(&d.elemd, elemd, s)) != hipSuccess)
         goto hip_fail;
+    d.zrow = d.elemd + zoff;
     if ((e = hipMalloc((void**)&d.windows, std::max<int64_t>(1, 2 * tl.n_tiles * T * E) * sizeof(int32_t))) !=
         hipSuccess)
         goto hip_fail;

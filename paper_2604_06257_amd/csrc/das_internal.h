@@ -37,6 +37,7 @@ struct PlanDev {
     float* tx = nullptr;       // [T][n_slots]
     int32_t* slot_vox = nullptr;  // [n_slots]
     double* elemd = nullptr;   // [E][3] element coordinates (float32 inputs held in FP64)
+    const void* zrow = nullptr; // 64 zero bytes (inside the elemd allocation): read for samples outside a record
     int32_t* windows = nullptr; // [n_tiles][T][E][2]: (first row, rows); plan-time only
     int4* items = nullptr;      // per tile, the (t, e, first row, rows) work items, e-major, in stages:
                                 // two int4 per stage for variants that pair (the second may be empty:

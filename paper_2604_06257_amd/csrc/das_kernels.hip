@@ -153,11 +153,17 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 // G element groups of 4 waves share the tile: group g takes items g, g + G,
 // ... and the groups' partial sums are added in a fixed order at the end.
 //
-// Software pipeline (per group, item k, prefetch depth 2):
-//   write the window of item k (registers, loaded two items ago) to LDS
-//   buffer k & 1 as rows (q[s], q[s+1] - q[s]); barrier
-//   issue the global loads of item k + 2G into the freed registers
-//   coefficients of item k (FP64), then FC frames of one LDS read + six FMAs
+// Software pipeline (per group; stage k = one item, or two for the variants that pair):
+//   write the window of stage k (registers) to LDS buffer k & 1 as rows
+//   (q[s], q[s+1] - q[s]); barrier; issue the global loads of a later stage
+//   into the freed registers; coefficients of stage k + G (FP64) while FC
+//   frames of one LDS read + six FMAs per item accumulate stage k.
+// Unpaired variants load stage k + 2G (two register sets, buffer loads over the
+// item's record, only where the window has rows).  Paired variants load stage
+// k + G into one register set with a branch-free fill: per-lane global loads of
+// either record, or of the plan's zero row for rows outside the record or the
+// windows; their scalar loads (items, element coordinates) are issued before
+// the barrier, whose wait then covers them.
 // Fill: thread -> (frame group of FPT frames, run of RPT rows); it loads RPT + 1
 // rows of its frames (each sample once) with 16-byte loads when aligned.
 // Waves per SIMD that the LDS footprint allows (the compiler may then spend
@@ -213,7 +219,6 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     float4* buf1 = buf0 + kBuf;
     const int fgrp = gt % NFG, row0 = (gt / NFG) * RPT;
     const int fbase = f0 + fgrp * FPT;
-    const bool full_frames = vec && (fbase + FPT <= kp.F);
 
     float acc_r[NTX * FC], acc_i[NTX * FC];
 #pragma unroll
@@ -228,20 +233,54 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     const int4* items = p.items + kIS * (int64_t)first;
     const int nsteps = (nitems + G - 1) / G;
 
-    // Channel data of one (t, e) record through a buffer resource: offsets
-    // outside [0, S * F) samples (rows before 0 or past S - 1) read as zero,
-    // which is the zero padding of the record.
+    // Channel data: record (t, e) holds S rows of F samples.  Rows outside [0, S) are the record's zero padding:
+    // a lane reads the plan's zero row for them (and for anything it does not need), so every load is in bounds
+    // and the fill has no branch on the thread.
     const int64_t rec_bytes = (int64_t)kp.S * kp.F * kEB;
     const int lane_off = fbase * kEB;  // this thread's frames within a row
     const int row_bytes = kp.F * kEB;
-    // byte offset of this thread's first stage row (relative to the window start) and frames: the per-item
-    // offsets are then a wave-uniform product plus this, with no per-lane multiply in the loop
-    const int lane_row_off = row0 * row_bytes + lane_off;
     const bool fill_frames = fbase < kp.F;
-    auto rsrc = [&](const int4& it) {
-        const char* rec = reinterpret_cast<const char*>(iq) + ((int64_t)it.x * kp.E + it.y) * rec_bytes;
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
+    // Loads are addressed as the IQ pointer plus a 64-bit byte offset per lane (the pointer keeps them global
+    // loads; an address rebuilt from an integer would make them flat loads, which also count against the LDS
+    // wait counter).  The zero row is reached through its offset from the IQ pointer.
+    const char* const gbase = reinterpret_cast<const char*>(iq);
+    const int64_t zoff = reinterpret_cast<const char*>(p.zrow) - gbase;
+    // Byte offset of record (t, e), formed on the scalar unit (items are wave-uniform) and kept opaque, so that a
+    // lane's choice between the two records of a stage is a select of two offsets, not a per-lane multiply.
+    auto record = [&](const int4& it) {
+        const int64_t a = ((int64_t)it.x * kp.E + it.y) * rec_bytes;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)a >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
     };
+    // Sample frames [fbase, fbase + FPT) of one row at byte offset o (used when ok, else the zero row): one load
+    // when the groups are aligned (kVec: the kernel argument vec, a separate pipeline so that the compiler cannot
+    // merge the two forms into 8-byte loads), else one per sample, frames past F reading the zero row (they feed
+    // no output).  Conditions are combined with & so that they stay selects, not branches.
+    auto load_group = [&](int64_t o, bool ok, Raw& dst, auto vec_tag) {
+        if constexpr (decltype(vec_tag)::value) {
+            dst = *reinterpret_cast<const Raw*>(gbase + (ok ? o : zoff));
+        } else {
+            uint32_t* w = reinterpret_cast<uint32_t*>(&dst);
+#pragma unroll
+            for (int q = 0; q < FPT; ++q) {
+                const bool okq = ok & (fbase + q < kp.F);
+                if (kEB == 8) {
+                    const uint2 v = *reinterpret_cast<const uint2*>(gbase + (okq ? o + q * 8 : zoff));
+                    w[2 * q] = v.x;
+                    w[2 * q + 1] = v.y;
+                } else {
+                    w[q] = *reinterpret_cast<const uint32_t*>(gbase + (okq ? o + q * 4 : zoff));
+                }
+            }
+        }
+    };
+    // Variants without stage pairs (one record per stage, 6 or more waves per SIMD) read through a buffer
+    // resource over the item's record, whose range check returns zero for offsets outside it (rows before 0 or
+    // past S - 1: the zero padding); only the fill threads with rows in the window load.  (The branch-free fill
+    // of the paired variants measured slower here: its per-lane addresses take registers that these variants'
+    // occupancy leaves to the multiply-accumulate's LDS reads.)
+    const bool full_frames = vec && (fbase + FPT <= kp.F);
     auto load_raw = [&](const __amdgpu_buffer_rsrc_t& rs, int off, Raw& dst) {
         if (full_frames) {
             if constexpr (sizeof(Raw) == 16) {
@@ -266,41 +305,65 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
             }
         }
     };
+    const int lane_row_off = row0 * row_bytes + lane_off;
+    auto load_single = [&](int k, Raw (&raw)[RPT + 1], float& txa, int4& ia, auto one_tx) {
+        ia = items[k];
+        if constexpr (decltype(one_tx)::value == 0) txa = p.tx[(int64_t)ia.x * kp.n_slots + slot];
+        if (row0 < ia.w && fill_frames) {
+            const char* rec = gbase + ((int64_t)ia.x * kp.E + ia.y) * rec_bytes;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(rec), (short)0, (int)rec_bytes, 0x00020000);
+            const int base = ia.z * row_bytes + lane_row_off;  // wave-uniform product plus a per-lane constant
+#pragma unroll
+            for (int j = 0; j <= RPT; ++j) load_raw(rs, base + j * row_bytes, raw[j]);
+        }
+    };
     // Stage rows 0 .. a.w - 1 are item a's window; item b's window starts at row bb(a) = a.w rounded up to a
     // multiple of RPT, so the RPT rows of a fill thread (and the sample after them) come from one record.
     auto bbase = [&](const int4& ia) { return (ia.w + RPT - 1) / RPT * RPT; };
-    auto load_item = [&](int k, Raw (&raw)[RPT + 1], float& txa, float& txb, int4& ia, int4& ib, auto one_tx) {
+    // The items of stage k (scalar loads).  The pipeline issues them, and the element coordinates below, just
+    // before a barrier: that barrier's wait for the LDS writes then covers them, and no scalar load is in flight
+    // during the multiply-accumulate (scalar loads return out of order, so one outstanding would turn every
+    // wait for an LDS read into a wait for all of them).
+    auto fetch_items = [&](int k, int4& ia, int4& ib, int64_t& reca, int64_t& recb) {
         ia = items[kIS * k];
         // without stage pairing the second item is a constant empty one and its code folds away
         ib = stage_pairs(FC) ? items[kIS * k + 1] : make_int4(0, 0, 0, 0);
+        reca = record(ia);
+        recb = record(ib);
+    };
+    struct ecrd {
+        double x, y, z;
+    };
+    auto elem_of = [&](const int4& it) {
+        const double* e = p.elemd + 3 * it.y;
+        return ecrd{e[0], e[1], e[2]};
+    };
+    // Transmit times and this fill thread's window rows of a stage's items (vector loads, in flight for two
+    // steps).  Sample row of stage row r: ia.z + r (first window) or ib.z + r - bb (second window).
+    auto issue_loads = [&](const int4& ia, const int4& ib, int64_t reca, int64_t recb, Raw (&raw)[RPT + 1],
+                           float& txa, float& txb, auto one_tx, auto vec_tag) {
         if constexpr (decltype(one_tx)::value == 0) {  // with one transmit its time is a per-lane constant
             txa = p.tx[(int64_t)ia.x * kp.n_slots + slot];
             txb = ib.w > 0 ? p.tx[(int64_t)ib.x * kp.n_slots + slot] : 0.0f;
         }
         const int bb = bbase(ia);
-        const bool in_b = ib.w > 0 && row0 >= bb;
-        if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
-            // sample row of stage row r: ia.z + r (first window) or ib.z + r - bb (second window)
-            const int base_a = ia.z * row_bytes;         // wave-uniform
-            const int base_b = (ib.z - bb) * row_bytes;  // wave-uniform
-            const int base = (in_b ? base_b : base_a) + lane_row_off;
-            // the record is uniform per thread but not per wave: two resources, each wave-uniform
-            const __amdgpu_buffer_rsrc_t ra = rsrc(ia);
-            const __amdgpu_buffer_rsrc_t rb = rsrc(ib.w > 0 ? ib : ia);
+        const bool in_b = (ib.w > 0) & (row0 >= bb);
+        const bool act = fill_frames & (row0 < (in_b ? bb + ib.w : ia.w));
+        const int r0 = (in_b ? ib.z - bb : ia.z) + row0;  // sample row of this thread's first stage row
+        const int off0 = r0 * row_bytes + lane_off;  // records are < 2 GiB: 32-bit offsets
+        const int64_t rec = in_b ? recb : reca;
 #pragma unroll
-            for (int j = 0; j <= RPT; ++j) {
-                const int off = base + j * row_bytes;
-                if (in_b) load_raw(rb, off, raw[j]);
-                else load_raw(ra, off, raw[j]);
-            }
-        }
+        for (int j = 0; j <= RPT; ++j)
+            load_group(rec + (uint32_t)(off0 + j * row_bytes), act & ((unsigned)(r0 + j) < (unsigned)kp.S), raw[j],
+                       vec_tag);
     };
     // LDS frame slot of frame f: frames of one fill thread go to slots NFG
     // apart, so the 16 lanes of a write hit 16 different bank groups.
-    auto store_item = [&](const int4& ia, const int4& ib, const Raw (&raw)[RPT + 1], float4* buf) {
-        const int bb = bbase(ia);
-        const bool in_b = ib.w > 0 && row0 >= bb;
-        if (row0 < (in_b ? bb + ib.w : ia.w) && fill_frames) {
+    // own: whether this thread writes its rows (paired variants: every thread that owns rows, zeros for rows
+    // outside the windows, which no lane reads; unpaired: the threads with rows in the window)
+    auto store_item = [&](const Raw (&raw)[RPT + 1], float4* buf, bool own) {
+        if (own) {
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 // when RPT does not divide the window rows, the last fill thread's run passes row kRows - 1:
@@ -332,17 +395,19 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     const das_txc tc0 = das_tx_const(p.tx[slot], kp);  // transmit 0
     // one_tx: a std::integral_constant<int, 0 | 1 | 2>: 0 = several transmits (cached receive part), 1 = one
     // transmit and a planar array, 2 = one transmit and elements at several depths.
-    auto coef_item = [&](const int4& it, float txv, bool live, int base, auto one_tx) {
+    // ee: the item's element coordinates when the caller fetched them early (paired variants); the unpaired
+    // variants read them here (a scalar load per item, or per element with several transmits).
+    auto coef_item = [&](const int4& it, const ecrd& ee, float txv, bool live, int base, auto one_tx) {
         das_coef c;
         if constexpr (decltype(one_tx)::value != 0) {
-            const double* e = p.elemd + 3 * it.y;
-            c = das_tx_setup(das_rx_setup_t<decltype(one_tx)::value == 1>(L, e[0], e[1], e[2], kp), tc0, kp);
+            const ecrd e = stage_pairs(FC) ? ee : elem_of(it);
+            c = das_tx_setup(das_rx_setup_t<decltype(one_tx)::value == 1>(L, e.x, e.y, e.z, kp), tc0, kp);
         } else {
             // marked unlikely (it is taken once per element, every T-th item), so that the compiler keeps
             // the branch rather than forming the receive part for every item
             if (__builtin_expect(it.y != last_e, 0)) {
-                const double* e = p.elemd + 3 * it.y;
-                rx = das_rx_setup(L, e[0], e[1], e[2], kp);
+                const ecrd e = stage_pairs(FC) ? ee : elem_of(it);
+                rx = das_rx_setup(L, e.x, e.y, e.z, kp);
                 last_e = it.y;
             }
             if (it.x != last_t) {
@@ -391,66 +456,102 @@ void das_kernel(PlanDev p, const void* __restrict__ iq, float2* __restrict__ out
     // coefficients are zero) multiplies zeros, never stale or unset LDS.
     for (int i = gt; i < 2 * kBuf; i += kSlots) buf0[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     __syncthreads();
-    auto pipeline = [&](auto one_tx) {
+    auto pipeline_pairs = [&](auto one_tx, auto vec_tag) {
         constexpr bool kOne = decltype(one_tx)::value != 0;
-        Raw ra[RPT + 1], rb[RPT + 1];
-        float txa0 = 0.0f, txa1 = 0.0f, txb0 = 0.0f, txb1 = 0.0f;
-        const int4 z4 = make_int4(0, 0, 0, 0);
-        int4 ia0 = z4, ia1 = z4, ib0 = z4, ib1 = z4;  // items (first, second) of pipeline slots a and b
-        if (grp < nitems) load_item(grp, ra, txa0, txa1, ia0, ia1, one_tx);
-        if (grp + G < nitems) load_item(grp + G, rb, txb0, txb1, ib0, ib1, one_tx);
+        if (nitems == 0) return;  // nothing to add: the sums stay zero
+        // Stage k's window is loaded during step k - G into one register set and written to LDS at the start
+        // of step k; items are fetched two stages ahead (scalar), element coordinates one stage ahead.  Every
+        // step loads and stores a window, so that the loads in flight are the same on every path (the compiler
+        // can then wait for exactly the ones it needs); stages past the tile's last repeat the last one's items
+        // and carry zero weights.
+        const int klast = nitems - 1;
+        Raw raw[RPT + 1];
+        float tn0 = 0.0f, tn1 = 0.0f;  // transmit times of stage k + G
+        int4 n0i, n1i, m0i, m1i;       // items of stages k + G and k + 2G
+        int64_t rn0, rn1, rm0, rm1;    // their record offsets
+        int4 c0i, c1i;                                         // items of stage grp (prologue)
+        int64_t rc0, rc1;
+        float tc0_ = 0.0f, tc1_ = 0.0f;
+        fetch_items(min(grp, klast), c0i, c1i, rc0, rc1);
+        issue_loads(c0i, c1i, rc0, rc1, raw, tc0_, tc1_, one_tx, vec_tag);
+        fetch_items(min(grp + G, klast), n0i, n1i, rn0, rn1);
         das_coef none;
         none.i0 = 0;
         none.row = 0;
         none.t = 0;
         none.beta = none.cr = none.ci = 0.0f;
-        // The second item's coefficients: with one transmit, always formed (zero weights when the stage has
-        // no second item), keeping the step one basic block; otherwise only when the stage has one (a
-        // wave-uniform branch: an empty item must not evict the cached receive geometry).
-        auto second = [&](const int4& i1, float tx1, bool has, int base) {
-            if constexpr (!stage_pairs(FC)) return none;
-            else if constexpr (kOne) return coef_item(i1, tx1, has, base, one_tx);
-            else return has ? coef_item(i1, tx1, true, base, one_tx) : none;
+        // The second item's coefficients: with one transmit, always formed (zero weights when the stage has no
+        // second item), keeping the step one basic block; otherwise only when the stage has one (a wave-uniform
+        // branch: an empty item must not evict the cached receive geometry).
+        auto second = [&](const int4& i1, const ecrd& e1, float tx1, bool has, int base) {
+            if constexpr (kOne) return coef_item(i1, e1, tx1, has, base, one_tx);
+            else return has ? coef_item(i1, e1, tx1, true, base, one_tx) : none;
         };
-        das_coef c0 = coef_item(ia0, txa0, grp < nitems, 0, one_tx);
-        bool two = grp < nitems && ia1.w > 0;
-        das_coef c1 = second(ia1, txa1, two, bbase(ia0));
+        das_coef c0 = coef_item(c0i, elem_of(c0i), tc0_, grp < nitems, 0, one_tx);
+        bool two = grp < nitems && c1i.w > 0;
+        das_coef c1 = second(c1i, elem_of(c1i), tc1_, two, bbase(c0i));
+        // One step (stage k): write stage k's window to its buffer; fetch the items of stage k + 2G and the
+        // element coordinates of stage k + G; barrier; load stage k + G's window and transmit times; form its
+        // coefficients while multiply-accumulating stage k.
+        auto step_p = [&](int k, float4* buf) {
+            store_item(raw, buf, row0 < kRows);
+            const ecrd e0 = elem_of(n0i), e1 = elem_of(n1i);
+            fetch_items(min(k + 2 * G, klast), m0i, m1i, rm0, rm1);
+            __syncthreads();
+            issue_loads(n0i, n1i, rn0, rn1, raw, tn0, tn1, one_tx, vec_tag);
+            const bool live = k + G < nitems;
+            const das_coef d0 = coef_item(n0i, e0, tn0, live, 0, one_tx);  // stage k + G
+            const bool ntwo = live && n1i.w > 0;
+            const das_coef d1 = second(n1i, e1, tn1, ntwo, bbase(n0i));
+            mac_item(c0, buf);
+            if (two) mac_item(c1, buf);
+            c0 = d0;
+            c1 = d1;
+            two = ntwo;
+            n0i = m0i;
+            n1i = m1i;
+            rn0 = rm0;
+            rn1 = rm1;
+        };
         for (int step = 0; step < nsteps; step += 2) {
-            {
-                const int k = step * G + grp;
-                if (k < nitems) store_item(ia0, ia1, ra, buf0);
-                __syncthreads();
-                if (k + 2 * G < nitems) load_item(k + 2 * G, ra, txa0, txa1, ia0, ia1, one_tx);
-                const bool live = k + G < nitems;
-                const das_coef n0 = coef_item(ib0, txb0, live, 0, one_tx);  // stage k + G
-                const bool ntwo = live && ib1.w > 0;
-                const das_coef n1 = second(ib1, txb1, ntwo, bbase(ib0));
-                mac_item(c0, buf0);
-                if (two) mac_item(c1, buf0);
-                c0 = n0;
-                c1 = n1;
-                two = ntwo;
-            }
-            if (step + 1 < nsteps) {
-                const int k = (step + 1) * G + grp;
-                if (k < nitems) store_item(ib0, ib1, rb, buf1);
-                __syncthreads();
-                if (k + 2 * G < nitems) load_item(k + 2 * G, rb, txb0, txb1, ib0, ib1, one_tx);
-                const bool live = k + G < nitems;
-                const das_coef n0 = coef_item(ia0, txa0, live, 0, one_tx);  // stage k + G
-                const bool ntwo = live && ia1.w > 0;
-                const das_coef n1 = second(ia1, txa1, ntwo, bbase(ia0));
-                mac_item(c0, buf1);
-                if (two) mac_item(c1, buf1);
-                c0 = n0;
-                c1 = n1;
-                two = ntwo;
-            }
+            step_p(step * G + grp, buf0);
+            if (step + 1 < nsteps) step_p((step + 1) * G + grp, buf1);
         }
     };
-    if (kp.T > 1) pipeline(std::integral_constant<int, 0>{});
-    else if (kp.planar) pipeline(std::integral_constant<int, 1>{});
-    else pipeline(std::integral_constant<int, 2>{});
+    // Unpaired variants: one item per stage, its loads and store only where the window has rows.
+    auto pipeline_single = [&](auto one_tx) {
+        Raw ra[RPT + 1], rb[RPT + 1];
+        float txa = 0.0f, txb = 0.0f;
+        const int4 z4 = make_int4(0, 0, 0, 0);
+        int4 ia = z4, ib = z4;
+        if (grp < nitems) load_single(grp, ra, txa, ia, one_tx);
+        if (grp + G < nitems) load_single(grp + G, rb, txb, ib, one_tx);
+        const ecrd none_e{0.0, 0.0, 0.0};
+        das_coef c0 = coef_item(ia, none_e, txa, grp < nitems, 0, one_tx);
+        auto step_s = [&](int k, Raw (&rx_)[RPT + 1], float& tx_, int4& i_, float ty, const int4 j, float4* buf) {
+            if (k < nitems) store_item(rx_, buf, row0 < i_.w && fill_frames);
+            __syncthreads();
+            if (k + 2 * G < nitems) load_single(k + 2 * G, rx_, tx_, i_, one_tx);
+            const das_coef n0 = coef_item(j, none_e, ty, k + G < nitems, 0, one_tx);  // stage k + G
+            mac_item(c0, buf);
+            c0 = n0;
+        };
+        for (int step = 0; step < nsteps; step += 2) {
+            step_s(step * G + grp, ra, txa, ia, txb, ib, buf0);
+            if (step + 1 < nsteps) step_s((step + 1) * G + grp, rb, txb, ib, txa, ia, buf1);
+        }
+    };
+    auto run = [&](auto one_tx) {
+        if constexpr (stage_pairs(FC)) {
+            if (vec) pipeline_pairs(one_tx, std::true_type{});
+            else pipeline_pairs(one_tx, std::false_type{});
+        } else {
+            pipeline_single(one_tx);
+        }
+    };
+    if (kp.T > 1) run(std::integral_constant<int, 0>{});
+    else if (kp.planar) run(std::integral_constant<int, 1>{});
+    else run(std::integral_constant<int, 2>{});
     if (G > 1) {
         // Fixed-order reduction of the groups' partial sums through LDS:
         // ((g0 + g1) + g2) + ...
