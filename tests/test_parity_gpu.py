@@ -474,6 +474,34 @@ def test_paired_stages_parity(kind, F, monkeypatch):
 _VARIANT_REFS = {}
 
 
+@pytest.mark.parametrize("F", [24, 23])
+@pytest.mark.parametrize("kind", ["c64", "f16"])
+def test_paired_fill_at_record_edges(F, kind, monkeypatch):
+    """The paired variants' fill reads a zero row for samples outside the record: a 12-sample record and t0 past
+    some delays put windows over row -1 and past the last row (the record's zero padding), with aligned (F = 24)
+    and per-sample (F = 23, odd) loads."""
+    iq, elem, vox, tx, p = small_case(1700 + F, T=2, E=16, S=12, F=F, V=300, t0=4e-7, depth=(0.3e-3, 1.0e-3))
+    if kind == "f16":
+        iq_t = torch.view_as_real(torch.from_numpy(iq)).to(torch.float16).contiguous()
+        iq_q = iq_t.float().numpy().view(np.complex64)[..., 0]
+    else:
+        iq_t, iq_q = torch.from_numpy(iq), iq
+    ref = oracle.das(iq_q, elem, vox, tx, **p)
+    # delays below t0 and past the record: both edges of the zero padding are in play
+    u = (tx[:, :, None] + np.linalg.norm(vox[None, :, None, :] - elem[None, None, :, :], axis=-1) / p["c"]
+         - p["t0"]) * p["fs"]
+    assert (np.floor(u) == -1).any() and (np.floor(u) == 11).any() and np.abs(ref).max() > 0
+    params = das.Params(n_tx=2, n_elem=16, n_samples=12, n_frames=F, n_vox=vox.shape[0], sound_speed=p["c"],
+                        fs=p["fs"], f_demod=p["fd"], t0=p["t0"], f_number=p["f_number"],
+                        tukey_alpha=p["tukey_alpha"])
+    for forced in [(16, 65, 2), (16, 33, 2), (32, 65, 2), (32, 41, 3)]:
+        monkeypatch.setenv("DAS_VARIANT", "%d,%d,%d" % forced)
+        with das.Plan(params, dev(elem), dev(vox), dev(tx)) as plan:
+            assert plan.info()["kernel"] == forced
+            y = plan.execute(iq_t.cuda()).cpu().numpy()
+        check_db(y, ref, "paired fill %s F=%d %s" % (forced, F, kind))
+
+
 @pytest.mark.parametrize("kind", ["c64", "f16", "bf16"])
 def test_every_kernel_variant(kind, monkeypatch):
     """Every compiled variant (forced through DAS_VARIANT), for each IQ type: parity with the FP64 oracle on the
