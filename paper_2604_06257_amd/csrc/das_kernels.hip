@@ -170,13 +170,14 @@ hipError_t launch_windows(const PlanDev& p, unsigned long long* counts_dev, hipS
 // registers on instruction-level parallelism instead of occupancy).
 // Variants that stage two items per step are capped so that the second item's registers (coefficients,
 // transmit time) fit without spilling: 4 waves (128 VGPRs) for 16 frames, 3 (168) for 32; unpaired 8-frame
-// variants run at 6 waves (85 VGPRs: their 16 accumulators do not fit 64; at 5 waves c3 ran 2.5 % slower), 4-frame
-// ones at 7 (73 VGPRs: at 8 they spilled, and the c2 grid at 4 frames ran 0.0347 against 0.0292 ms).
+// variants run at 6 waves (85 VGPRs: their 16 accumulators do not fit 64; at 5 waves c3 ran 2.5 % slower), or 5
+// with several element groups (at 6 they spilled; the c2 grid at 8 frames 0.0363 -> 0.0356 ms), 4-frame ones at 7
+// (73 VGPRs: at 8 they spilled, and the c2 grid at 4 frames ran 0.0347 against 0.0292 ms).
 template <int FC, int P, int G>
 constexpr int das_waves_per_simd() {
     constexpr int bytes = G * 2 * FC * P * 16;
     constexpr int wgs = (160 * 1024) / bytes;
-    constexpr int cap = !stage_pairs(FC) ? (FC >= 8 ? 6 : (FC >= 4 ? 7 : 8)) : (FC >= 32 ? 3 : 4);
+    constexpr int cap = !stage_pairs(FC) ? (FC >= 8 ? (G >= 2 ? 5 : 6) : (FC >= 4 ? 7 : 8)) : (FC >= 32 ? 3 : 4);
     return (wgs * G) < 1 ? 1 : ((wgs * G) > cap ? cap : wgs * G);
 }
 
